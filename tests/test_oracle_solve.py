@@ -1,0 +1,91 @@
+"""Pins of the oracle's whole CPR-FGMRES solve and the adaptive-setup rule.
+
+* Whole solve on shrunken grids agrees with a dense LAPACK solve within
+  cond(A) * tol.
+* FP32 preconditioner model: same iteration count within 10% and the true
+  relative residual below tol.
+* ASCPR (Section 4): mu = 0 rebuilds on every step and gives iterates
+  identical to plain CPR-GMRES with a fresh SETUP each step; mu = infinity
+  builds once; the relative rule rebuilds exactly when the previous count
+  exceeds factor * It_ref; decisions depend on the iteration history only.
+"""
+import numpy as np
+
+from oracle import ascpr, cpr, fgmres
+from workloads import blackoil as bo
+
+
+def _solve(case, b, dtype=np.float64, tol=1e-6):
+    A = cpr.Bsr.from_case(case)
+    B = cpr.setup(A, dtype=dtype)
+    return A, fgmres.fgmres(lambda v: cpr.bsr_matvec(A, v), B.apply, b, tol=tol)
+
+
+def test_whole_solve_matches_dense_direct():
+    for shape in ((6, 6, 3), (10, 10, 4)):
+        case = bo.case_spe10_like(seed=41, shape=shape, inactive_frac=0.05)
+        b = bo.rhs(case.ndof, 42)
+        A, res = _solve(case, b)
+        d = A.to_dense()
+        x = np.linalg.solve(d, b)
+        assert res.converged and res.relres_true < 1e-6
+        err = np.linalg.norm(res.x - x) / np.linalg.norm(x)
+        assert err <= np.linalg.cond(d) * 1e-6
+
+
+def test_fp32_preconditioner_model_iterations():
+    case = bo.case_spe10_like(seed=43, shape=(16, 14, 8))
+    b = bo.rhs(case.ndof, 44)
+    _, r64 = _solve(case, b)
+    _, r32 = _solve(case, b, dtype=np.float32)
+    assert r32.converged and r32.relres_true < 1e-6
+    assert abs(r32.iterations - r64.iterations) <= max(1, 0.1 * r64.iterations)
+
+
+def test_decide_rebuild_rules():
+    d = ascpr.decide_rebuild
+    assert d(1, 0, 0)
+    assert d(5, 3, 3, mode="mu", mu=0)
+    assert not d(5, 20, 3, mode="mu", mu=20)
+    assert d(5, 21, 3, mode="mu", mu=20)
+    assert not d(5, 13, 10, mode="factor", factor=1.3)
+    assert d(5, 14, 10, mode="factor", factor=1.3)
+    assert d(5, 1, 10, mode="factor", size_changed=True)
+
+
+def _sequence(n=4, shape=(10, 9, 5)):
+    return [(cpr.Bsr.from_case(c), b) for _, c, b in bo.newton_sequence(n_steps=n, shape=shape)]
+
+
+def test_mu_zero_is_plain_cpr_every_step():
+    steps = _sequence()
+    reps = ascpr.solve_sequence(steps, mode="mu", mu=0)
+    assert all(r.rebuilt for r in reps)
+    for (A, b), r in zip(steps, reps):
+        B = cpr.setup(A)
+        res = fgmres.fgmres(lambda v: cpr.bsr_matvec(A, v), B.apply, b)
+        assert res.iterations == r.iterations and res.relres_true == r.relres_true
+
+
+def test_mu_infinite_single_setup_and_history_determinism():
+    steps = _sequence()
+    reps = ascpr.solve_sequence(steps, mode="mu", mu=10 ** 9)
+    assert [r.rebuilt for r in reps] == [True, False, False, False]
+    assert all(r.converged for r in reps)
+    again = ascpr.solve_sequence(steps, mode="mu", mu=10 ** 9)
+    assert [(r.iterations, r.relres_true) for r in again] == [(r.iterations, r.relres_true) for r in reps]
+
+
+def test_factor_rule_follows_history():
+    steps = _sequence(n=5)
+    reps = ascpr.solve_sequence(steps, mode="factor", factor=1.3)
+    it_ref = None
+    prev = None
+    for k, r in enumerate(reps, start=1):
+        if k == 1:
+            assert r.rebuilt
+        else:
+            assert r.rebuilt == (prev > 1.3 * it_ref)
+        if r.rebuilt:
+            it_ref = r.iterations
+        prev = r.iterations
