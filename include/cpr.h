@@ -1,0 +1,142 @@
+/*
+ * cpr.h - C ABI of the MI355X CPR-FGMRES solver for 3x3-block black-oil
+ * Jacobians.
+ *
+ * Method: Zhao, Feng, Zhang, Shu, "Parallel Multi-Stage Preconditioners with
+ * Adaptive Setup for the Black Oil Model" (arXiv 2201.01970).
+ *   - the preconditioner B is CPR, Section 3.1, eq. (CPR):
+ *       I - B A = (I - R A)(I - Pi_P B_P Pi_P^T A),
+ *     applied as in Algorithm "CPR method" (stage 1: pressure AMG V-cycle
+ *     smoothed by the PGS-SCM multi-colour Gauss-Seidel of Section 5.2;
+ *     stage 2: multi-colour block Gauss-Seidel);
+ *   - the outer solver is restarted flexible GMRES (Section 4, Algorithm
+ *     "ASCPR-GMRES") and SETUP is reused across Newton steps by the adaptive
+ *     rule of Algorithm "ASCPR";
+ *   - a change of matrix size always needs a new SETUP (the Remark following
+ *     Algorithm "ASCPR"): here that is a new handle.
+ *
+ * All functions are C, never throw, and report failure through cpr_status.
+ * Device pointers are HIP device addresses on the GPU that is current when
+ * cpr_setup is called; every kernel of a handle runs on the handle's stream.
+ */
+#ifndef CPR_MI355X_CPR_H
+#define CPR_MI355X_CPR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CPR_OK = 0,
+  CPR_NOT_CONVERGED = 1,        /* warning: x holds the last iterate, info is filled */
+  CPR_ERR_INVALID_ARG = -1,     /* bad sizes, block_dim != 3, unsorted columns, missing diagonal */
+  CPR_ERR_PATTERN_MISMATCH = -2,/* update_values with a different sparsity pattern */
+  CPR_ERR_SIZE_MISMATCH = -3,   /* update_values with a different size */
+  CPR_ERR_SINGULAR_BLOCK = -4,  /* a 3x3 diagonal block has no usable pivot */
+  CPR_ERR_SINGULAR_COARSE = -5, /* the coarsest AMG matrix has no usable pivot */
+  CPR_ERR_NAN = -6,             /* NaN or Inf in the right-hand side or the iteration */
+  CPR_ERR_OOM = -7,             /* device allocation failed */
+  CPR_ERR_HIP = -8              /* any other HIP runtime error */
+} cpr_status;
+
+typedef enum { CPR_MEM_HOST = 0, CPR_MEM_DEVICE = 1 } cpr_mem;
+
+/* A 3x3-block CSR (BSR) matrix (Section 2.2: three primary unknowns per
+ * cell, so the reservoir Jacobian is a sparse matrix of 3x3 blocks).
+ * row_ptr[n_block_rows+1] and col_idx[nnz_blocks] are int32; the columns of
+ * each block row are strictly ascending and include the diagonal block.
+ * values holds nnz_blocks*9 doubles, each block row-major.  The unknowns of
+ * cell i are 3i (pressure), 3i+1, 3i+2 (saturations).  `location` says
+ * whether the three arrays are host or device memory.  The library deep-copies
+ * them; the caller keeps ownership. */
+typedef struct {
+  int32_t n_block_rows;
+  int32_t nnz_blocks;
+  int32_t block_dim; /* must be 3 */
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const double* values;
+  int32_t location; /* cpr_mem */
+} cpr_bsr;
+
+/* Solver parameters.  Defaults (cpr_params_default) in brackets. */
+typedef struct {
+  int32_t restart;        /* FGMRES restart length m [30] (Section 6 uses m = 28) */
+  int32_t max_restarts;   /* maximum restart cycles [100] (MaxIt of Algorithm ASCPR-GMRES) */
+  double theta_rs;        /* RS coarsening strength threshold [0.25] */
+  double theta_color;     /* colouring threshold theta of eq. (strong-matrix) [0.05] */
+  int32_t coarse_max;     /* stop coarsening at or below this many rows [50] */
+  int32_t max_levels;     /* maximum AMG levels [25] */
+  int32_t pre_sweeps;     /* PGS-SCM pre-smoothing sweeps [2] */
+  int32_t post_sweeps;    /* PGS-SCM post-smoothing sweeps [2] */
+  int32_t precond_fp32;   /* 1: preconditioner stored and computed in FP32 (FP64
+                             outer FGMRES, FP64 coarsest solve) [0] */
+  int32_t reuse_mode;     /* 0: SETUP before every solve on new values;
+                             1: paper rule, reuse iff It^(k-1) <= mu;
+                             2: relative rule, reuse iff It^(k-1) <= reuse_factor*It_ref [2] */
+  int32_t mu;             /* threshold of reuse_mode 1 [20] */
+  double reuse_factor;    /* factor of reuse_mode 2 [1.3] */
+} cpr_params;
+
+typedef struct {
+  int32_t iterations;   /* inner FGMRES steps (one B apply + one A product each) */
+  int32_t restarts;     /* completed restart cycles before the final one */
+  int32_t rebuilt;      /* 1 if SETUP ran for this solve */
+  int32_t n_levels;     /* AMG levels of the hierarchy in use */
+  double relres_true;   /* ||b - A x||_2 / ||b||_2 in FP64, recomputed at exit */
+  double relres_est;    /* last Givens estimate |g_{j+1}| / ||r_0|| */
+  double setup_ms;      /* host wall time of SETUP in this call (0 when reused) */
+  double solve_ms;      /* host wall time of the Krylov iteration */
+} cpr_solve_info;
+
+typedef struct cpr_handle cpr_handle;
+
+/* Fill *p with the defaults listed above. */
+void cpr_params_default(cpr_params* p);
+
+/* SETUP (Algorithm "CPR method" viewed as producing B, the Remark after
+ * Algorithm "ASCPR"): validate and copy A into device memory, build the
+ * pressure AMG hierarchy (strength on the GPU; colouring, C/F split,
+ * interpolation and Galerkin products on the host), the stage-2 block
+ * colouring and diagonal-block inverses, and the Krylov workspace.
+ * hip_stream: the hipStream_t all work of the handle runs on (NULL = the
+ * default stream); the caller keeps ownership of it.
+ * Returns CPR_OK and *out, or an error (then *out is NULL). */
+cpr_status cpr_setup(const cpr_bsr* A, const cpr_params* p, void* hip_stream, cpr_handle** out);
+
+/* Replace the values of A (same n_block_rows, nnz_blocks, row_ptr, col_idx;
+ * the pattern is compared through a 64-bit hash).  The outer FGMRES uses the
+ * new values at the next solve; whether the preconditioner is rebuilt is
+ * decided there by the adaptive rule (Algorithm "ASCPR"); a singular diagonal
+ * block is reported by the solve that rebuilds.  Errors:
+ * CPR_ERR_SIZE_MISMATCH, CPR_ERR_PATTERN_MISMATCH. */
+cpr_status cpr_update_values(cpr_handle* h, const cpr_bsr* A);
+
+/* Solve A x = b to ||b - A x|| / ||b - A x_in|| < tol with CPR-FGMRES
+ * (Algorithm "ASCPR-GMRES").  b and x are caller-owned device arrays of
+ * 3*n_block_rows doubles; x is the initial guess on entry and the solution
+ * on exit.  Blocks until the result is in x.  info may be NULL. */
+cpr_status cpr_solve(cpr_handle* h, const double* b, double* x, double tol, cpr_solve_info* info);
+
+/* Make subsequent work of h run on hip_stream (a hipStream_t, NULL = the
+ * default stream) after draining the previous stream. */
+cpr_status cpr_set_stream(cpr_handle* h, void* hip_stream);
+
+/* Free every resource of h (NULL is allowed). */
+void cpr_destroy(cpr_handle* h);
+
+const char* cpr_status_string(cpr_status s);
+
+/* Text of the last error recorded on h (empty string if none). */
+const char* cpr_last_error(const cpr_handle* h);
+
+/* Device bytes held by h (matrices, hierarchy, workspace). */
+int64_t cpr_device_bytes(const cpr_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPR_MI355X_CPR_H */

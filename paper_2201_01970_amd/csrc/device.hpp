@@ -1,0 +1,139 @@
+// Device data layouts and kernel launchers of the CPR solve phase (gfx950).
+//
+// Layout: every sparse matrix is stored as SELL-64 ("sliced ELLPACK"): rows are
+// grouped in slices of 64 consecutive rows, one row per lane of a 64-wide
+// wavefront; slice s occupies slots [slice_ptr[s], slice_ptr[s+1]), slot t of a
+// slice holds the t-th stored entry of each of its 64 rows, lane-contiguous,
+// so a wavefront streams each slot with fully coalesced loads while every lane
+// still sums its own row sequentially in stored order.  Rows shorter than the
+// slice width are padded with column -1.  For 3x3 blocks the nine values of a
+// slot are stored as nine lane-contiguous planes (value e of lane l of slot t
+// at (t*9 + e)*64 + l).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cpr {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;  // threads per workgroup for row kernels (4 slices)
+constexpr int32_t kPadCol = -1;
+constexpr int32_t kEarlierBit = 1 << 30;  // stage-2 column flag: neighbour of an earlier colour
+constexpr int32_t kColMask = kEarlierBit - 1;
+
+template <typename T>
+struct SellView {
+  int32_t n_rows = 0;
+  const int32_t* slice_ptr = nullptr;
+  const int32_t* col = nullptr;
+  const T* val = nullptr;
+};
+
+// Kernel classes whose launches can be timed with HIP events.
+struct LaunchTimer {
+  virtual ~LaunchTimer() = default;
+  virtual void begin(int kind, hipStream_t s) = 0;
+  virtual void end(int kind, hipStream_t s, double bytes) = 0;
+};
+
+// ---- fine-level (3x3 BSR) kernels ----
+// y = A x  (resid == nullptr)  or  y = b - A x (b != nullptr).  A: FP64 or FP32
+// values; x: FP64 or FP32; y and b: FP64.
+template <typename TA, typename TX>
+void launch_bsr_spmv(const SellView<TA>& A, const TX* x, const double* b, double* y, hipStream_t s);
+
+// rp[p] = v[3*perm[p]] (pressure restriction, with cast)
+template <typename T>
+void launch_restrict_pressure(int32_t n, const double* v, const int32_t* perm, T* rp, hipStream_t s);
+
+// pe[perm[p]] = e[p]
+template <typename T>
+void launch_scatter(int32_t n, const T* e, const int32_t* perm, T* pe, hipStream_t s);
+
+// One block colour [lo, hi) of the stage-2 block Gauss-Seidel fused with the
+// CPR prolongation and residual (rows in block-colour order, cell[q] = cell).
+template <typename T>
+void launch_stage2(const SellView<T>& A, int32_t lo, int32_t hi, const int32_t* cell, const T* dinv,
+                   int32_t dinv_ld, const double* v, const T* pe, T* z, hipStream_t s);
+
+// Inverse of the diagonal blocks (LU with partial pivoting), planes dinv[e*ld + q];
+// diag_pos[q] = index of the diagonal block of cell cell[q] in the input BSR.
+// singular[0] is set to 1 when a pivot is below 1e-300 * max|block|.
+template <typename T>
+void launch_block_inverse(int32_t n, const double* vals, const int64_t* diag_pos, T* dinv, int32_t ld,
+                          int32_t* singular, hipStream_t s);
+
+// Scatter BSR values (row-major blocks in input order) into a block SELL layout
+// given slot positions pos[k] (slot index of input block k, lane included).
+template <typename T>
+void launch_bsr_values_to_sell(int64_t nnzb, const double* vals, const int64_t* pos, T* sell_val,
+                               hipStream_t s);
+
+// ---- AMG level kernels (CSR in SELL-64, rows in colour order) ----
+// One colour [lo, hi): x_i = (b_i - sum_{j != i} a_ij xt_j) / a_ii, where xt_j is
+// s_in[j] for j in [lo, hi) and x[j] otherwise; zero_start: x = 0 on entry, so
+// only j < lo contribute.  Writes x[i] and s_out[i].
+template <typename T>
+void launch_gs_colour(const SellView<T>& A, const T* diag, int32_t lo, int32_t hi, const T* b, T* x,
+                      const T* s_in, T* s_out, bool zero_start, hipStream_t s);
+
+// r = b - A x (stored order, diagonal included)
+template <typename T>
+void launch_csr_residual(const SellView<T>& A, const T* b, const T* x, T* r, hipStream_t s);
+
+// y = A x (sum from 0 in stored order)
+template <typename T>
+void launch_csr_spmv(const SellView<T>& A, const T* x, T* y, hipStream_t s);
+
+// x_i = x_i + (sum_J p_iJ e_J); snap[i] = x_i
+template <typename T>
+void launch_prolong_add(const SellView<T>& P, const T* e, T* x, T* snap, hipStream_t s);
+
+// Dense LU solve on one workgroup: x = A^{-1} b with FP64 factors.
+template <typename T>
+void launch_coarse_solve(int32_t n, const double* lu, const int32_t* piv, const T* b, T* x, hipStream_t s);
+
+// ---- setup kernel: strength masks (bit 1: RS strength, bit 2: eq. (strong-matrix))
+void launch_strength(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, double theta_rs,
+                     double theta_color, uint8_t* mask, hipStream_t s);
+
+// ---- vector helpers ----
+template <typename TS, typename TD>
+void launch_gather(int32_t n, const TS* src, const int32_t* perm, TD* dst, hipStream_t s);  // dst[p]=src[perm[p]]
+template <typename TS, typename TD>
+void launch_scatter_cast(int32_t n, const TS* src, const int32_t* perm, TD* dst, hipStream_t s);  // dst[perm[p]]=src[p]
+template <typename T>
+void launch_fill(int64_t n, T value, T* dst, hipStream_t s);
+template <typename TS, typename TD>
+void launch_copy_cast(int64_t n, const TS* src, TD* dst, hipStream_t s);
+void launch_copy_bytes(int64_t n_bytes, const void* src, void* dst, hipStream_t s);
+
+// ---- Krylov kernels (FP64) ----
+int krylov_grid(int64_t n);
+// partial[i*grid + blk] = partial dot of w with V[j0+i] (i < nb); V row stride ld
+void launch_multidot(int64_t n, const double* w, const double* V, int64_t ld, int j0, int nb, double* partial,
+                     hipStream_t s);
+// out[i] = sum over blocks of partial[i*grid + blk] (fixed order), for i < count
+void launch_reduce_partials(const double* partial, int grid, int count, double* out, hipStream_t s);
+// w -= sum_i h[i] * V[j0+i] for i < nb; if norm_partial: partial sums of w^2
+void launch_axpy_norm(int64_t n, double* w, const double* V, int64_t ld, int j0, int nb, const double* h,
+                      double* norm_partial, hipStream_t s);
+// partial sums of v^2
+void launch_norm_partial(int64_t n, const double* v, double* partial, hipStream_t s);
+// v = w / h[0]  (h on device)
+void launch_scale_div(int64_t n, const double* w, const double* h, double* v, hipStream_t s);
+// Givens step j of the Hessenberg column; see krylov.hip
+void launch_givens(int m, int j, const double* norm_partial, int grid, double* H, double* cs, double* sn,
+                   double* g, double* hnorm, double* report, hipStream_t s);
+// set g = 0 except g[0] = norm (from the partials); report[0..1]; v-scale factor
+void launch_start_cycle(int m, const double* norm_partial, int grid, double* g, double* hnorm, double* report,
+                        hipStream_t s);
+// y = H(0:k,0:k)^{-1} g(0:k) (upper triangular), H column-major with ld m+1
+void launch_backsolve(int m, int k, const double* H, const double* g, double* y, hipStream_t s);
+// x += sum_{i<k} y[i] * Z[i]
+template <typename TZ>
+void launch_update_x(int64_t n, double* x, const TZ* Z, int64_t ld, int k, const double* y, hipStream_t s);
+
+}  // namespace cpr

@@ -1,0 +1,404 @@
+// Host-side SETUP algorithms; see host_setup.hpp for the contracts.
+#include "host_setup.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <queue>
+#include <utility>
+
+namespace cpr {
+
+Pattern pattern_from_mask(const HostCsr& A, const std::vector<uint8_t>& mask, uint8_t bit) {
+  Pattern S;
+  S.n = A.n_rows;
+  S.ptr.assign(A.n_rows + 1, 0);
+  for (int32_t i = 0; i < A.n_rows; ++i) {
+    int32_t c = 0;
+    for (int32_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) c += (mask[p] & bit) ? 1 : 0;
+    S.ptr[i + 1] = S.ptr[i] + c;
+  }
+  S.col.resize(S.ptr[A.n_rows]);
+  for (int32_t i = 0; i < A.n_rows; ++i) {
+    int32_t w = S.ptr[i];
+    for (int32_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p)
+      if (mask[p] & bit) S.col[w++] = A.col[p];
+  }
+  return S;
+}
+
+Pattern transpose_pattern(const Pattern& S) {
+  Pattern T;
+  T.n = S.n;
+  T.ptr.assign(S.n + 1, 0);
+  for (int32_t c : S.col) T.ptr[c + 1]++;
+  for (int32_t i = 0; i < S.n; ++i) T.ptr[i + 1] += T.ptr[i];
+  T.col.resize(S.col.size());
+  std::vector<int32_t> fill(T.ptr.begin(), T.ptr.end() - 1);
+  for (int32_t i = 0; i < S.n; ++i)  // rows ascending -> each T row ascending
+    for (int32_t p = S.ptr[i]; p < S.ptr[i + 1]; ++p) T.col[fill[S.col[p]]++] = i;
+  return T;
+}
+
+// ------------------------------------------------------------ grouping
+namespace {
+enum : int8_t { kOutside = 0, kUndecided = 1, kInW = 2, kInWbar = 3 };
+
+// Max-heap on (influence, -index): largest influence first, then smallest index.
+struct InflKey {
+  int32_t infl, v;
+};
+struct InflLess {
+  bool operator()(const InflKey& a, const InflKey& b) const {
+    if (a.infl != b.infl) return a.infl < b.infl;
+    return a.v > b.v;
+  }
+};
+using InflHeap = std::priority_queue<InflKey, std::vector<InflKey>, InflLess>;
+}  // namespace
+
+int32_t vertices_grouping(const Pattern& S, std::vector<int32_t>& colour) {
+  const int32_t n = S.n;
+  colour.assign(n, -1);
+  std::vector<int32_t> infl(n);
+  for (int32_t i = 0; i < n; ++i) infl[i] = S.ptr[i + 1] - S.ptr[i];
+  std::vector<int8_t> state(n, kOutside);
+  std::vector<int32_t> V(n);
+  for (int32_t i = 0; i < n; ++i) V[i] = i;
+  std::vector<int32_t> Wbar;
+  int32_t c = 0;
+  while (!V.empty()) {
+    for (int32_t v : V) state[v] = kUndecided;
+    int64_t remaining = static_cast<int64_t>(V.size());
+    std::vector<InflKey> init;
+    init.reserve(V.size());
+    for (int32_t v : V) init.push_back({infl[v], v});
+    InflHeap heap_v(InflLess(), std::move(init));
+    InflHeap heap_f;
+    Wbar.clear();
+    auto pop = [&](InflHeap& h) -> int32_t {
+      while (!h.empty()) {
+        int32_t v = h.top().v;
+        h.pop();
+        if (state[v] == kUndecided) return v;
+      }
+      return -1;
+    };
+    while (remaining > 0) {
+      int32_t v = pop(heap_f);
+      if (v < 0) v = pop(heap_v);
+      bool touches_w = false;
+      for (int32_t p = S.ptr[v]; p < S.ptr[v + 1]; ++p)
+        if (state[S.col[p]] == kInW) {
+          touches_w = true;
+          break;
+        }
+      if (!touches_w) {
+        state[v] = kInW;
+        colour[v] = c;
+        --remaining;
+        for (int32_t p = S.ptr[v]; p < S.ptr[v + 1]; ++p) {
+          int32_t j = S.col[p];
+          if (state[j] == kUndecided) {
+            state[j] = kInWbar;
+            Wbar.push_back(j);
+            --remaining;
+          }
+        }
+        for (int32_t p = S.ptr[v]; p < S.ptr[v + 1]; ++p) {
+          int32_t k = S.col[p];
+          for (int32_t q = S.ptr[k]; q < S.ptr[k + 1]; ++q) {
+            int32_t j = S.col[q];
+            if (state[j] == kUndecided) heap_f.push({infl[j], j});
+          }
+        }
+      } else {
+        state[v] = kInWbar;
+        Wbar.push_back(v);
+        --remaining;
+      }
+    }
+    // W-bar (ascending) is the next round's vertex set; reset visited marks.
+    for (int32_t v : V) state[v] = kOutside;
+    std::sort(Wbar.begin(), Wbar.end());
+    V.swap(Wbar);
+    ++c;
+  }
+  return c;
+}
+
+// ------------------------------------------------------------ RS split
+namespace {
+struct LamKey {
+  int64_t lam;
+  int32_t i;
+};
+struct LamLess {
+  bool operator()(const LamKey& a, const LamKey& b) const {
+    if (a.lam != b.lam) return a.lam < b.lam;
+    return a.i > b.i;
+  }
+};
+}  // namespace
+
+void rs_split(const Pattern& S, const Pattern& ST, std::vector<int8_t>& cf) {
+  constexpr int8_t U = 0, C = 1, F = 2;
+  const int32_t n = S.n;
+  cf.assign(n, U);
+  std::vector<int64_t> lam(n, 0);
+  std::vector<LamKey> init;
+  for (int32_t i = 0; i < n; ++i) {
+    const bool no_s = S.ptr[i + 1] == S.ptr[i];
+    const bool no_st = ST.ptr[i + 1] == ST.ptr[i];
+    if (no_s && no_st) {
+      cf[i] = F;
+    } else {
+      lam[i] = ST.ptr[i + 1] - ST.ptr[i];
+      init.push_back({lam[i], i});
+    }
+  }
+  std::priority_queue<LamKey, std::vector<LamKey>, LamLess> heap(LamLess(), std::move(init));
+  while (!heap.empty()) {
+    LamKey top = heap.top();
+    heap.pop();
+    const int32_t i = top.i;
+    if (cf[i] != U || top.lam != lam[i]) continue;  // stale entry
+    if (lam[i] == 0) break;
+    cf[i] = C;
+    for (int32_t p = ST.ptr[i]; p < ST.ptr[i + 1]; ++p) {
+      const int32_t j = ST.col[p];
+      if (cf[j] != U) continue;
+      cf[j] = F;
+      for (int32_t q = S.ptr[j]; q < S.ptr[j + 1]; ++q) {
+        const int32_t k = S.col[q];
+        if (cf[k] == U) {
+          lam[k] += 1;
+          heap.push({lam[k], k});
+        }
+      }
+    }
+    for (int32_t p = S.ptr[i]; p < S.ptr[i + 1]; ++p) {
+      const int32_t j = S.col[p];
+      if (cf[j] == U) {
+        lam[j] -= 1;
+        heap.push({lam[j], j});
+      }
+    }
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    if (cf[i] != U) continue;
+    bool has_c = false;
+    for (int32_t p = S.ptr[i]; p < S.ptr[i + 1]; ++p)
+      if (cf[S.col[p]] == C) {
+        has_c = true;
+        break;
+      }
+    cf[i] = has_c ? F : C;
+  }
+  // second pass: membership of C_i tracked with a stamp array
+  std::vector<int32_t> stamp(n, -1);
+  for (int32_t i = 0; i < n; ++i) {
+    if (cf[i] != F) continue;
+    for (int32_t p = S.ptr[i]; p < S.ptr[i + 1]; ++p)
+      if (cf[S.col[p]] == C) stamp[S.col[p]] = i;
+    int32_t tentative = -1;
+    for (int32_t p = S.ptr[i]; p < S.ptr[i + 1]; ++p) {
+      const int32_t j = S.col[p];
+      if (cf[j] != F) continue;
+      bool shares = false;
+      for (int32_t q = S.ptr[j]; q < S.ptr[j + 1]; ++q)
+        if (stamp[S.col[q]] == i) {
+          shares = true;
+          break;
+        }
+      if (shares) continue;
+      if (tentative < 0) {
+        tentative = j;
+        cf[j] = C;
+        stamp[j] = i;
+      } else {
+        cf[tentative] = F;
+        stamp[tentative] = -1;
+        cf[i] = C;
+        break;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ interpolation
+// For F point i with interpolatory set C_i = strong C dependencies (stored order):
+//   d = a_ii; then d = d + a_ij for each weak j != i in stored order;
+//   num_j = a_ij for j in C_i;
+//   for each strong F dependency m of i (stored order):
+//     den = 0 + sum of a_mk over k in C_i (row m, stored order);
+//     den == 0 -> d = d + a_im; otherwise num_k = num_k + (a_im*a_mk)/den for
+//     each k in C_i met in row m (stored order);
+//   w_ij = -num_j / d.
+// C points get the unit row of their coarse index; F points without a strong C
+// dependency get an empty row.
+bool rs_interpolation(const HostCsr& A, const std::vector<uint8_t>& mask, uint8_t bit,
+                      const std::vector<int8_t>& cf, HostCsr& P) {
+  constexpr int8_t C = 1, F = 2;
+  const int32_t n = A.n_rows;
+  std::vector<int32_t> coarse(n, -1);
+  int32_t nc = 0;
+  for (int32_t i = 0; i < n; ++i)
+    if (cf[i] == C) coarse[i] = nc++;
+  P = HostCsr();
+  P.n_rows = n;
+  P.n_cols = nc;
+  P.ptr.assign(n + 1, 0);
+  std::vector<int32_t> in_ci(n, -1);
+  std::vector<double> num(n, 0.0);
+  bool ok = true;
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t a0 = A.ptr[i], a1 = A.ptr[i + 1];
+    if (cf[i] == C) {
+      P.col.push_back(coarse[i]);
+      P.val.push_back(1.0);
+      P.ptr[i + 1] = static_cast<int32_t>(P.col.size());
+      continue;
+    }
+    bool any_c = false;
+    for (int32_t p = a0; p < a1; ++p)
+      if ((mask[p] & bit) && cf[A.col[p]] == C) {
+        in_ci[A.col[p]] = i;
+        num[A.col[p]] = A.val[p];
+        any_c = true;
+      }
+    if (!any_c) {
+      P.ptr[i + 1] = static_cast<int32_t>(P.col.size());
+      continue;
+    }
+    double d = 0.0;
+    for (int32_t p = a0; p < a1; ++p)
+      if (A.col[p] == i) d = A.val[p];
+    for (int32_t p = a0; p < a1; ++p)
+      if (A.col[p] != i && !(mask[p] & bit)) d = d + A.val[p];
+    for (int32_t p = a0; p < a1; ++p) {
+      const int32_t m = A.col[p];
+      if (!(mask[p] & bit) || cf[m] != F) continue;
+      const double a_im = A.val[p];
+      double den = 0.0;
+      for (int32_t q = A.ptr[m]; q < A.ptr[m + 1]; ++q)
+        if (in_ci[A.col[q]] == i) den = den + A.val[q];
+      if (den == 0.0) {
+        d = d + a_im;
+        continue;
+      }
+      for (int32_t q = A.ptr[m]; q < A.ptr[m + 1]; ++q) {
+        const int32_t k = A.col[q];
+        if (in_ci[k] == i) num[k] = num[k] + (a_im * A.val[q]) / den;
+      }
+    }
+    if (d == 0.0) ok = false;
+    for (int32_t p = a0; p < a1; ++p) {
+      const int32_t j = A.col[p];
+      if ((mask[p] & bit) && cf[j] == C) {
+        P.col.push_back(coarse[j]);
+        P.val.push_back(-num[j] / d);
+      }
+    }
+    P.ptr[i + 1] = static_cast<int32_t>(P.col.size());
+  }
+  return ok;
+}
+
+HostCsr transpose(const HostCsr& A) {
+  HostCsr T;
+  T.n_rows = A.n_cols;
+  T.n_cols = A.n_rows;
+  T.ptr.assign(A.n_cols + 1, 0);
+  for (int32_t c : A.col) T.ptr[c + 1]++;
+  for (int32_t i = 0; i < A.n_cols; ++i) T.ptr[i + 1] += T.ptr[i];
+  T.col.resize(A.col.size());
+  T.val.resize(A.val.size());
+  std::vector<int32_t> fill(T.ptr.begin(), T.ptr.end() - 1);
+  for (int32_t i = 0; i < A.n_rows; ++i)
+    for (int32_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+      const int32_t w = fill[A.col[p]]++;
+      T.col[w] = i;
+      T.val[w] = A.val[p];
+    }
+  return T;
+}
+
+HostCsr spgemm_ordered(const HostCsr& A, const HostCsr& B) {
+  HostCsr Cm;
+  Cm.n_rows = A.n_rows;
+  Cm.n_cols = B.n_cols;
+  Cm.ptr.assign(A.n_rows + 1, 0);
+  std::vector<double> acc(B.n_cols, 0.0);
+  std::vector<int32_t> seen(B.n_cols, -1);
+  std::vector<int32_t> touched;
+  for (int32_t i = 0; i < A.n_rows; ++i) {
+    touched.clear();
+    for (int32_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+      const int32_t k = A.col[p];
+      const double a = A.val[p];
+      for (int32_t q = B.ptr[k]; q < B.ptr[k + 1]; ++q) {
+        const int32_t j = B.col[q];
+        if (seen[j] != i) {
+          seen[j] = i;
+          acc[j] = 0.0;
+          touched.push_back(j);
+        }
+        const double prod = a * B.val[q];
+        acc[j] = acc[j] + prod;
+      }
+    }
+    std::sort(touched.begin(), touched.end());
+    for (int32_t j : touched) {
+      Cm.col.push_back(j);
+      Cm.val.push_back(acc[j]);
+    }
+    Cm.ptr[i + 1] = static_cast<int32_t>(Cm.col.size());
+  }
+  return Cm;
+}
+
+bool dense_lu(int32_t n, std::vector<double>& a, std::vector<int32_t>& piv) {
+  piv.assign(n, 0);
+  for (int32_t k = 0; k < n; ++k) {
+    int32_t p = k;
+    double best = std::fabs(a[static_cast<size_t>(k) * n + k]);
+    for (int32_t r = k + 1; r < n; ++r) {
+      const double v = std::fabs(a[static_cast<size_t>(r) * n + k]);
+      if (v > best) {
+        best = v;
+        p = r;
+      }
+    }
+    piv[k] = p;
+    if (best == 0.0) return false;
+    if (p != k)
+      for (int32_t c = 0; c < n; ++c) std::swap(a[static_cast<size_t>(k) * n + c], a[static_cast<size_t>(p) * n + c]);
+    const double inv = a[static_cast<size_t>(k) * n + k];
+    for (int32_t r = k + 1; r < n; ++r) {
+      double& l = a[static_cast<size_t>(r) * n + k];
+      l = l / inv;
+      for (int32_t c = k + 1; c < n; ++c) {
+        const double prod = l * a[static_cast<size_t>(k) * n + c];
+        a[static_cast<size_t>(r) * n + c] = a[static_cast<size_t>(r) * n + c] - prod;
+      }
+    }
+  }
+  return true;
+}
+
+uint64_t pattern_hash(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](uint32_t v) {
+    for (int b = 0; b < 4; ++b) {
+      h ^= (v >> (8 * b)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  };
+  mix(static_cast<uint32_t>(n));
+  mix(static_cast<uint32_t>(nnz));
+  for (int32_t i = 0; i <= n; ++i) mix(static_cast<uint32_t>(row_ptr[i]));
+  for (int32_t p = 0; p < nnz; ++p) mix(static_cast<uint32_t>(col[p]));
+  return h;
+}
+
+}  // namespace cpr

@@ -1,0 +1,308 @@
+// The CPR preconditioner on the device (Section 3.1, Algorithm "CPR method"):
+// stage 1 = one V-cycle of the pressure AMG smoothed by PGS-SCM (Section 5.2),
+// stage 2 = one forward multi-colour block Gauss-Seidel sweep, fused with the
+// prolongation Pi_P and the residual r = v - A z.
+#include <algorithm>
+#include <numeric>
+
+#include "solver.hpp"
+
+namespace cpr {
+
+namespace {
+
+// Host SELL-64 image of a CSR matrix with rows in `order` and columns mapped
+// through `colmap`; entries keep their stored order.
+struct SellHost {
+  int32_t n_rows = 0;
+  std::vector<int32_t> slice_ptr, col;
+  std::vector<double> val;
+};
+
+SellHost build_sell(const HostCsr& A, const std::vector<int32_t>& order, const std::vector<int32_t>& colmap) {
+  SellHost S;
+  const int32_t n = static_cast<int32_t>(order.size());
+  S.n_rows = n;
+  const int32_t ns = (n + kWave - 1) / kWave;
+  S.slice_ptr.assign(ns + 1, 0);
+  for (int32_t s = 0; s < ns; ++s) {
+    int32_t w = 0;
+    for (int32_t p = s * kWave; p < std::min(n, (s + 1) * kWave); ++p) {
+      const int32_t i = order[p];
+      w = std::max(w, A.ptr[i + 1] - A.ptr[i]);
+    }
+    S.slice_ptr[s + 1] = S.slice_ptr[s] + w;
+  }
+  const int64_t slots = S.slice_ptr[ns];
+  S.col.assign(static_cast<size_t>(slots) * kWave, kPadCol);
+  S.val.assign(static_cast<size_t>(slots) * kWave, 0.0);
+  for (int32_t p = 0; p < n; ++p) {
+    const int32_t i = order[p], s = p / kWave, lane = p % kWave;
+    int32_t t = S.slice_ptr[s];
+    for (int32_t q = A.ptr[i]; q < A.ptr[i + 1]; ++q, ++t) {
+      const size_t e = static_cast<size_t>(t) * kWave + lane;
+      S.col[e] = colmap.empty() ? A.col[q] : colmap[A.col[q]];
+      S.val[e] = A.val[q];
+    }
+  }
+  return S;
+}
+
+template <typename T>
+DevSell<T> upload_sell(Arena& ar, const SellHost& S) {
+  DevSell<T> D;
+  D.n_rows = S.n_rows;
+  D.slots = S.slice_ptr.empty() ? 0 : S.slice_ptr.back();
+  D.slice_ptr = ar.upload(S.slice_ptr);
+  D.col = ar.upload(S.col);
+  std::vector<T> v(S.val.begin(), S.val.end());
+  D.val = ar.upload(v);
+  return D;
+}
+
+std::vector<int32_t> inverse_perm(const std::vector<int32_t>& perm) {
+  std::vector<int32_t> inv(perm.size());
+  for (size_t p = 0; p < perm.size(); ++p) inv[perm[p]] = static_cast<int32_t>(p);
+  return inv;
+}
+
+}  // namespace
+
+template <typename T>
+class Precond final : public PrecondBase {
+ public:
+  struct Level {
+    int32_t n = 0;
+    int64_t nnz = 0, nnz_p = 0, nnz_r = 0;
+    std::vector<int32_t> coff;
+    std::vector<double> colour_bytes;  // algorithmic bytes of each colour launch
+    DevSell<T> A, P, R;
+    T *diag = nullptr, *x = nullptr, *b = nullptr, *r = nullptr, *s0 = nullptr, *s1 = nullptr;
+    int32_t* perm = nullptr;
+  };
+
+  Precond(const cpr_params& prm, int32_t n_b, const std::vector<HostLevel>& hl, const std::vector<double>& lu,
+          const std::vector<int32_t>& piv, const std::vector<int32_t>& bperm, const std::vector<int32_t>& bcoff,
+          const std::vector<int32_t>& h_row_ptr, const std::vector<int32_t>& h_col,
+          const std::vector<int32_t>& bcolour, const double* d_vals_in, hipStream_t s)
+      : pre_(prm.pre_sweeps), post_(prm.post_sweeps), n_b_(n_b) {
+    const int nl = static_cast<int>(hl.size());
+    lv_.resize(nl);
+    const double sv = sizeof(T);
+    std::vector<std::vector<int32_t>> inv(nl);
+    for (int l = 0; l < nl; ++l) inv[l] = inverse_perm(hl[l].perm);
+    for (int l = 0; l < nl; ++l) {
+      Level& L = lv_[l];
+      const HostLevel& H = hl[l];
+      L.n = H.A.n_rows;
+      L.nnz = H.A.nnz();
+      L.coff = H.coff;
+      L.perm = ar_.upload(H.perm);
+      L.x = ar_.alloc<T>(L.n);
+      L.b = ar_.alloc<T>(L.n);
+      if (l + 1 < nl) {
+        L.A = upload_sell<T>(ar_, build_sell(H.A, H.perm, inv[l]));
+        std::vector<T> dg(L.n);
+        for (int32_t p = 0; p < L.n; ++p) {
+          const int32_t i = H.perm[p];
+          double d = 0.0;
+          for (int32_t q = H.A.ptr[i]; q < H.A.ptr[i + 1]; ++q)
+            if (H.A.col[q] == i) d = H.A.val[q];
+          dg[p] = static_cast<T>(d);
+        }
+        L.diag = ar_.upload(dg);
+        L.r = ar_.alloc<T>(L.n);
+        L.s0 = ar_.alloc<T>(L.n);
+        L.s1 = ar_.alloc<T>(L.n);
+        L.P = upload_sell<T>(ar_, build_sell(H.P, H.perm, inv[l + 1]));
+        const HostCsr R = transpose(H.P);
+        L.R = upload_sell<T>(ar_, build_sell(R, hl[l + 1].perm, inv[l]));
+        L.nnz_p = H.P.nnz();
+        L.nnz_r = R.nnz();
+        for (size_t c = 0; c + 1 < L.coff.size(); ++c) {
+          int64_t nz = 0;
+          for (int32_t p = L.coff[c]; p < L.coff[c + 1]; ++p) {
+            const int32_t i = H.perm[p];
+            nz += H.A.ptr[i + 1] - H.A.ptr[i];
+          }
+          const int64_t rows = L.coff[c + 1] - L.coff[c];
+          L.colour_bytes.push_back(nz * (sv + 4.0) + 4.0 * rows + 4.0 * rows * sv);
+        }
+      }
+    }
+    nL_ = lv_.back().n;
+    lu_ = ar_.upload(lu);
+    piv_ = ar_.upload(piv);
+
+    // ---- fine level for stage 2: cells in block-colour order
+    bcoff_ = bcoff;
+    cell_ = ar_.upload(bperm);
+    const int32_t n = n_b;
+    const int32_t ns = (n + kWave - 1) / kWave;
+    std::vector<int32_t> sp(ns + 1, 0);
+    for (int32_t s2 = 0; s2 < ns; ++s2) {
+      int32_t w = 0;
+      for (int32_t q = s2 * kWave; q < std::min(n, (s2 + 1) * kWave); ++q) {
+        const int32_t i = bperm[q];
+        w = std::max(w, h_row_ptr[i + 1] - h_row_ptr[i]);
+      }
+      sp[s2 + 1] = sp[s2] + w;
+    }
+    const int64_t slots = sp[ns];
+    std::vector<int32_t> col(static_cast<size_t>(slots) * kWave, kPadCol);
+    std::vector<int64_t> pos(h_col.size());
+    std::vector<int64_t> diag_pos(n);
+    stage2_bytes_.assign(bcoff.size() > 0 ? bcoff.size() - 1 : 0, 0.0);
+    for (int32_t q = 0; q < n; ++q) {
+      const int32_t i = bperm[q], s2 = q / kWave, lane = q % kWave;
+      int32_t t = sp[s2];
+      int cidx = bcolour[i];
+      for (int32_t k = h_row_ptr[i]; k < h_row_ptr[i + 1]; ++k, ++t) {
+        const size_t e = static_cast<size_t>(t) * kWave + lane;
+        const int32_t j = h_col[k];
+        const bool earlier = bcolour[j] < bcolour[i];
+        col[e] = j | (earlier ? kEarlierBit : 0);
+        pos[k] = static_cast<int64_t>(e);
+        if (j == i) diag_pos[q] = k;
+        stage2_bytes_[cidx] += (earlier ? 9.0 : 3.0) * sv + 4.0;
+      }
+      stage2_bytes_[cidx] += 24.0 + 13.0 * sv;
+    }
+    fine_.n_rows = n;
+    fine_.slots = slots;
+    fine_.slice_ptr = ar_.upload(sp);
+    fine_.col = ar_.upload(col);
+    fine_.val = ar_.alloc<T>(slots * 9 * kWave);
+    HIPCHK(hipMemsetAsync(fine_.val, 0, static_cast<size_t>(slots) * 9 * kWave * sizeof(T), s));
+    int64_t* d_pos = ar_.alloc<int64_t>(static_cast<int64_t>(pos.size()));
+    HIPCHK(hipMemcpy(d_pos, pos.data(), pos.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    launch_bsr_values_to_sell<T>(static_cast<int64_t>(pos.size()), d_vals_in, d_pos, fine_.val, s);
+    int64_t* d_diag_pos = ar_.alloc<int64_t>(n);
+    HIPCHK(hipMemcpy(d_diag_pos, diag_pos.data(), diag_pos.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    dinv_ld_ = n;
+    dinv_ = ar_.alloc<T>(static_cast<int64_t>(9) * n);
+    int32_t* d_sing = ar_.alloc<int32_t>(1);
+    HIPCHK(hipMemsetAsync(d_sing, 0, sizeof(int32_t), s));
+    launch_block_inverse<T>(n, d_vals_in, d_diag_pos, dinv_, dinv_ld_, d_sing, s);
+    int32_t sing = 0;
+    HIPCHK(hipMemcpyAsync(&sing, d_sing, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (sing) throw Error(CPR_ERR_SINGULAR_BLOCK, "a 3x3 diagonal block is singular");
+    pe_ = ar_.alloc<T>(n);
+  }
+
+  void apply(const double* v, void* zv, hipStream_t s) override {
+    T* z = static_cast<T*>(zv);
+    Level& L0 = lv_[0];
+    launch_restrict_pressure<T>(L0.n, v, L0.perm, L0.b, s);
+    vcycle(0, s);
+    launch_scatter<T>(L0.n, L0.x, L0.perm, pe_, s);
+    const SellView<T> F = fine_.view();
+    for (size_t c = 0; c + 1 < bcoff_.size(); ++c) {
+      if (timer) timer->begin(CPR_KSTAT_STAGE2, s);
+      launch_stage2<T>(F, bcoff_[c], bcoff_[c + 1], cell_, dinv_, dinv_ld_, v, pe_, z, s);
+      if (timer) timer->end(CPR_KSTAT_STAGE2, s, stage2_bytes_[c]);
+    }
+  }
+
+  void vcycle_own(const double* r, double* e, hipStream_t s) override {
+    Level& L0 = lv_[0];
+    launch_gather<double, T>(L0.n, r, L0.perm, L0.b, s);
+    vcycle(0, s);
+    launch_scatter_cast<T, double>(L0.n, L0.x, L0.perm, e, s);
+  }
+
+  void smooth_own(int l, double* x, const double* b, int sweeps, bool zero_start, hipStream_t s) override {
+    if (l < 0 || l + 1 >= static_cast<int>(lv_.size())) throw Error(CPR_ERR_INVALID_ARG, "level has no smoother");
+    Level& L = lv_[l];
+    launch_gather<double, T>(L.n, b, L.perm, L.b, s);
+    launch_gather<double, T>(L.n, x, L.perm, L.x, s);
+    int cur = 0;
+    if (!zero_start) launch_copy_cast<T, T>(L.n, L.x, L.s0, s);
+    for (int w = 0; w < sweeps; ++w) {
+      sweep(l, cur, zero_start && w == 0, s);
+      cur ^= 1;
+    }
+    launch_scatter_cast<T, double>(L.n, L.x, L.perm, x, s);
+  }
+
+  int n_levels() const override { return static_cast<int>(lv_.size()); }
+  bool fp32() const override { return sizeof(T) == 4; }
+  int64_t bytes() const override { return ar_.bytes(); }
+
+ private:
+  void sweep(int l, int cur, bool zero, hipStream_t s) {
+    Level& L = lv_[l];
+    T* S[2] = {L.s0, L.s1};
+    const SellView<T> A = L.A.view();
+    for (size_t c = 0; c + 1 < L.coff.size(); ++c) {
+      const bool timed = timer && l == 0;
+      if (timed) timer->begin(CPR_KSTAT_SMOOTH_L0, s);
+      launch_gs_colour<T>(A, L.diag, L.coff[c], L.coff[c + 1], L.b, L.x, S[cur], S[cur ^ 1], zero, s);
+      if (timed) timer->end(CPR_KSTAT_SMOOTH_L0, s, L.colour_bytes[c]);
+    }
+  }
+
+  void vcycle(int l, hipStream_t s) {
+    Level& L = lv_[l];
+    const int nl = static_cast<int>(lv_.size());
+    if (l == nl - 1) {
+      launch_coarse_solve<T>(L.n, lu_, piv_, L.b, L.x, s);
+      return;
+    }
+    const double sv = sizeof(T);
+    int cur = 0;
+    if (pre_ == 0) launch_fill<T>(L.n, (T)0, L.x, s);
+    for (int w = 0; w < pre_; ++w) {
+      sweep(l, cur, w == 0, s);
+      cur ^= 1;
+    }
+    Level& C = lv_[l + 1];
+    const bool timed = timer && l == 0;
+    if (timed) timer->begin(CPR_KSTAT_TRANSFER_L0, s);
+    launch_csr_residual<T>(L.A.view(), L.b, L.x, L.r, s);
+    if (timed) timer->end(CPR_KSTAT_TRANSFER_L0, s, L.nnz * (sv + 4) + 4.0 * L.n + 3.0 * L.n * sv);
+    if (timed) timer->begin(CPR_KSTAT_TRANSFER_L0, s);
+    launch_csr_spmv<T>(L.R.view(), L.r, C.b, s);
+    if (timed) timer->end(CPR_KSTAT_TRANSFER_L0, s, L.nnz_r * (sv + 4) + 4.0 * C.n + L.n * sv + C.n * sv);
+    vcycle(l + 1, s);
+    T* S[2] = {L.s0, L.s1};
+    if (timed) timer->begin(CPR_KSTAT_TRANSFER_L0, s);
+    launch_prolong_add<T>(L.P.view(), C.x, L.x, S[cur], s);
+    if (timed) timer->end(CPR_KSTAT_TRANSFER_L0, s, L.nnz_p * (sv + 4) + 4.0 * L.n + C.n * sv + 2.0 * L.n * sv);
+    for (int w = 0; w < post_; ++w) {
+      sweep(l, cur, false, s);
+      cur ^= 1;
+    }
+  }
+
+  Arena ar_;
+  std::vector<Level> lv_;
+  int pre_, post_;
+  int32_t n_b_;
+  int32_t nL_ = 0;
+  double* lu_ = nullptr;
+  int32_t* piv_ = nullptr;
+  std::vector<int32_t> bcoff_;
+  int32_t* cell_ = nullptr;
+  DevSell<T> fine_;
+  T* dinv_ = nullptr;
+  int32_t dinv_ld_ = 0;
+  T* pe_ = nullptr;
+  std::vector<double> stage2_bytes_;
+};
+
+std::unique_ptr<PrecondBase> make_precond(bool fp32, const cpr_params& prm, int32_t n_b,
+                                          const std::vector<HostLevel>& hl, const std::vector<double>& lu,
+                                          const std::vector<int32_t>& piv, const std::vector<int32_t>& bperm,
+                                          const std::vector<int32_t>& bcoff, const std::vector<int32_t>& h_row_ptr,
+                                          const std::vector<int32_t>& h_col, const std::vector<int32_t>& bcolour,
+                                          const double* d_vals_in, hipStream_t s) {
+  if (fp32)
+    return std::make_unique<Precond<float>>(prm, n_b, hl, lu, piv, bperm, bcoff, h_row_ptr, h_col, bcolour,
+                                            d_vals_in, s);
+  return std::make_unique<Precond<double>>(prm, n_b, hl, lu, piv, bperm, bcoff, h_row_ptr, h_col, bcolour,
+                                           d_vals_in, s);
+}
+
+}  // namespace cpr

@@ -1,0 +1,383 @@
+// SETUP pipeline and the FP64 flexible GMRES driver with the adaptive-setup
+// rule (Section 4, Algorithms "ASCPR-GMRES" and "ASCPR").
+#include "solver.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+
+namespace cpr {
+
+void hip_check(hipError_t e, const char* what, const char* file, int line) {
+  if (e == hipSuccess) return;
+  (void)hipGetLastError();
+  const cpr_status st = (e == hipErrorOutOfMemory) ? CPR_ERR_OOM : CPR_ERR_HIP;
+  throw Error(st, std::string(hipGetErrorString(e)) + " in " + what + " (" + file + ":" + std::to_string(line) + ")");
+}
+
+// ------------------------------------------------------------------ profiler
+Profiler::~Profiler() {
+  for (auto& r : pending_) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : free_) (void)hipEventDestroy(e);
+  for (hipEvent_t e : open_ev_)
+    if (e) (void)hipEventDestroy(e);
+}
+
+void Profiler::enable(bool on) {
+  on_ = on;
+  if (on)
+    for (int k = 0; k < CPR_KSTAT_COUNT; ++k) {
+      launches[k] = 0;
+      total_ms[k] = 0.0;
+      bytes[k] = 0.0;
+    }
+}
+
+hipEvent_t Profiler::get_event() {
+  if (!free_.empty()) {
+    hipEvent_t e = free_.back();
+    free_.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  return e;
+}
+
+void Profiler::begin(int kind, hipStream_t s) {
+  if (!on_) return;
+  hipEvent_t e = get_event();
+  HIPCHK(hipEventRecord(e, s));
+  open_ev_[kind] = e;
+}
+
+void Profiler::end(int kind, hipStream_t s, double b) {
+  if (!on_ || !open_ev_[kind]) return;
+  hipEvent_t e = get_event();
+  HIPCHK(hipEventRecord(e, s));
+  pending_.push_back({kind, open_ev_[kind], e, b});
+  open_ev_[kind] = nullptr;
+}
+
+void Profiler::collect() {
+  for (auto& r : pending_) {
+    HIPCHK(hipEventSynchronize(r.b));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    launches[r.kind] += 1;
+    total_ms[r.kind] += ms;
+    bytes[r.kind] += r.bytes;
+    free_.push_back(r.a);
+    free_.push_back(r.b);
+  }
+  pending_.clear();
+}
+
+namespace {
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Rows of each colour, longest rows first (fewer padded SELL slots), then by
+// index; returns the permutation (device position -> row) and colour offsets.
+void colour_order(int32_t n, const std::vector<int32_t>& ptr, const std::vector<int32_t>& colour, int32_t ncol,
+                  std::vector<int32_t>& perm, std::vector<int32_t>& coff) {
+  perm.resize(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
+    if (colour[a] != colour[b]) return colour[a] < colour[b];
+    const int32_t la = ptr[a + 1] - ptr[a], lb = ptr[b + 1] - ptr[b];
+    if (la != lb) return la > lb;
+    return a < b;
+  });
+  coff.assign(ncol + 1, 0);
+  for (int32_t i = 0; i < n; ++i) coff[colour[i] + 1]++;
+  for (int32_t c = 0; c < ncol; ++c) coff[c + 1] += coff[c];
+}
+
+}  // namespace
+
+}  // namespace cpr
+
+using namespace cpr;
+
+// ------------------------------------------------------------------ SETUP
+// Pressure extraction (A_PP = Pi_P^T A Pi_P, the (0,0) entry of every stored
+// block), then per level: strength masks on the GPU, RS split, interpolation
+// and Galerkin product on the host, until the level is small enough; then the
+// colouring of every smoothed level (Algorithm VerticesGrouping on eq.
+// (strong-matrix)), the coarsest LU, the stage-2 block colouring (theta = 0
+// on the block graph) and the device images.
+void cpr_handle::build_precond() {
+  const double t0 = now_ms();
+  if (!h_vals_valid) {
+    h_vals.resize(static_cast<size_t>(nnz_b) * 9);
+    HIPCHK(hipMemcpy(h_vals.data(), d_vals_in, h_vals.size() * sizeof(double), hipMemcpyDeviceToHost));
+    h_vals_valid = true;
+  }
+  pc.reset();
+  hl.clear();
+
+  HostCsr A;
+  A.n_rows = A.n_cols = n_b;
+  A.ptr = h_row_ptr;
+  A.col = h_col;
+  A.val.resize(nnz_b);
+  for (int32_t k = 0; k < nnz_b; ++k) A.val[k] = h_vals[static_cast<size_t>(k) * 9];
+
+  Arena tmp;
+  int32_t *d_ptr = nullptr, *d_col = nullptr;
+  double* d_val = nullptr;
+  uint8_t* d_mask = nullptr;
+  int64_t cap_n = 0, cap_nnz = 0;
+  while (true) {
+    HostLevel L;
+    L.A = std::move(A);
+    const int32_t n = L.A.n_rows;
+    const bool last = n <= prm.coarse_max || static_cast<int>(hl.size()) + 1 >= prm.max_levels;
+    if (last) {
+      hl.push_back(std::move(L));
+      break;
+    }
+    // strength masks on the device
+    if (n + 1 > cap_n || L.A.nnz() > cap_nnz) {
+      tmp.release();
+      cap_n = n + 1;
+      cap_nnz = std::max<int64_t>(1, L.A.nnz());
+      d_ptr = tmp.alloc<int32_t>(cap_n);
+      d_col = tmp.alloc<int32_t>(cap_nnz);
+      d_val = tmp.alloc<double>(cap_nnz);
+      d_mask = tmp.alloc<uint8_t>(cap_nnz);
+    }
+    HIPCHK(hipMemcpyAsync(d_ptr, L.A.ptr.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(d_col, L.A.col.data(), L.A.nnz() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(d_val, L.A.val.data(), L.A.nnz() * sizeof(double), hipMemcpyHostToDevice, stream));
+    launch_strength(n, d_ptr, d_col, d_val, prm.theta_rs, prm.theta_color, d_mask, stream);
+    L.mask.resize(L.A.nnz());
+    HIPCHK(hipMemcpyAsync(L.mask.data(), d_mask, L.A.nnz(), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+
+    const Pattern S = pattern_from_mask(L.A, L.mask, 1);
+    const Pattern ST = transpose_pattern(S);
+    rs_split(S, ST, L.cf);
+    int32_t nc = 0;
+    for (int8_t c : L.cf) nc += (c == 1);
+    if (nc == 0 || static_cast<double>(nc) > 0.9 * n) {
+      L.cf.clear();
+      hl.push_back(std::move(L));
+      break;
+    }
+    if (!rs_interpolation(L.A, L.mask, 1, L.cf, L.P))
+      throw Error(CPR_ERR_SINGULAR_COARSE, "zero interpolation denominator");
+    const HostCsr R = transpose(L.P);
+    const HostCsr AP = spgemm_ordered(L.A, L.P);
+    A = spgemm_ordered(R, AP);
+    hl.push_back(std::move(L));
+  }
+  tmp.release();
+
+  const int nl = static_cast<int>(hl.size());
+  for (int l = 0; l < nl; ++l) {
+    HostLevel& L = hl[l];
+    if (l + 1 < nl) {
+      const Pattern Sc = pattern_from_mask(L.A, L.mask, 2);
+      L.n_colours = vertices_grouping(Sc, L.colour);
+      colour_order(L.A.n_rows, L.A.ptr, L.colour, L.n_colours, L.perm, L.coff);
+    } else {
+      L.perm.resize(L.A.n_rows);
+      std::iota(L.perm.begin(), L.perm.end(), 0);
+    }
+  }
+  // coarsest dense LU (FP64)
+  const HostCsr& Ac = hl.back().A;
+  const int32_t nc = Ac.n_rows;
+  if (nc > 8192) throw Error(CPR_ERR_INVALID_ARG, "coarsening stalled above 8192 rows");
+  std::vector<double> lu(static_cast<size_t>(nc) * nc, 0.0);
+  for (int32_t i = 0; i < nc; ++i)
+    for (int32_t q = Ac.ptr[i]; q < Ac.ptr[i + 1]; ++q) lu[static_cast<size_t>(i) * nc + Ac.col[q]] += Ac.val[q];
+  std::vector<int32_t> piv;
+  if (!dense_lu(nc, lu, piv)) throw Error(CPR_ERR_SINGULAR_COARSE, "coarsest matrix is singular");
+
+  // stage-2 block colouring: theta = 0 on the block graph
+  Pattern B;
+  B.n = n_b;
+  B.ptr.assign(n_b + 1, 0);
+  for (int32_t i = 0; i < n_b; ++i) {
+    for (int32_t k = h_row_ptr[i]; k < h_row_ptr[i + 1]; ++k) {
+      const int32_t j = h_col[k];
+      if (j == i) continue;
+      bool nz = false;
+      for (int e = 0; e < 9; ++e) nz = nz || h_vals[static_cast<size_t>(k) * 9 + e] != 0.0;
+      if (nz) B.col.push_back(j);
+    }
+    B.ptr[i + 1] = static_cast<int32_t>(B.col.size());
+  }
+  n_block_colours = vertices_grouping(B, block_colour);
+  std::vector<int32_t> bperm, bcoff;
+  colour_order(n_b, h_row_ptr, block_colour, n_block_colours, bperm, bcoff);
+
+  pc = make_precond(prm.precond_fp32 != 0, prm, n_b, hl, lu, piv, bperm, bcoff, h_row_ptr, h_col, block_colour,
+                    d_vals_in, stream);
+  pc->timer = &prof;
+  HIPCHK(hipStreamSynchronize(stream));
+  values_changed = false;
+  last_setup_ms = now_ms() - t0;
+}
+
+void cpr_handle::spmv(const double* x, double* y) {
+  launch_bsr_spmv<double, double>(outer.view(), x, nullptr, y, stream);
+}
+
+// ------------------------------------------------------------------ SOLVE
+// Flexible GMRES(m), classical Gram-Schmidt, Givens rotations.  Convergence:
+// ||r|| / ||r_0|| < tol checked on the Givens estimate after every step and
+// confirmed with the true residual; iterations = inner steps.
+cpr_status cpr_handle::solve(const double* b, double* x, double tol, cpr_solve_info* info) {
+  // adaptive setup (Algorithm "ASCPR"); SETUP of cpr_setup counts as k = 1
+  k_solves += 1;
+  bool rebuild = false;
+  if (k_solves > 1 && values_changed) {
+    if (prm.reuse_mode == 0)
+      rebuild = true;
+    else if (prm.reuse_mode == 1)
+      rebuild = !(it_prev <= prm.mu);
+    else
+      rebuild = !(static_cast<double>(it_prev) <= prm.reuse_factor * static_cast<double>(it_ref));
+  }
+  double setup_ms = 0.0;
+  if (rebuild) {
+    build_precond();
+    setup_ms = last_setup_ms;
+  } else if (k_solves == 1) {
+    setup_ms = 0.0;
+  }
+  const bool fresh = rebuild || k_solves == 1;
+
+  const double t0 = now_ms();
+  const int64_t N = 3 * static_cast<int64_t>(n_b);
+  const int grid = krylov_grid(N);
+  const bool f32 = pc->fp32();
+  const int64_t ld = N;
+  auto Zj = [&](int j) -> void* {
+    return f32 ? static_cast<void*>(static_cast<float*>(Z) + j * ld) : static_cast<void*>(static_cast<double*>(Z) + j * ld);
+  };
+  auto sync_report = [&]() {
+    HIPCHK(hipMemcpyAsync(report_h, report_d, 4 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+  };
+  auto outer_spmv_resid = [&](const double* xx, const double* bb, double* rr) {
+    if (prof.on()) prof.begin(CPR_KSTAT_SPMV, stream);
+    launch_bsr_spmv<double, double>(outer.view(), xx, bb, rr, stream);
+    if (prof.on())
+      prof.end(CPR_KSTAT_SPMV, stream, 9.0 * nnz_b * 8 + 4.0 * nnz_b + 4.0 * (n_b + 1) + 3.0 * n_b * (8 + 8 + 8));
+  };
+
+  // ||b|| (for the reported true relative residual), r0 = b - A x0, beta0 = ||r0||
+  launch_norm_partial(N, b, norm_partial, stream);
+  launch_reduce_partials(norm_partial, grid, 1, report_d + 2, stream);
+  outer_spmv_resid(x, b, r);
+  launch_norm_partial(N, r, norm_partial, stream);
+  launch_start_cycle(m, norm_partial, grid, g, hnorm, report_d, stream);
+  sync_report();
+  const double beta0 = report_h[0];
+  const double bnorm = std::sqrt(report_h[2]);
+  int its = 0, cycles = 0;
+  double est = 1.0, rel = 0.0, relb = 0.0;
+  cpr_status st = CPR_NOT_CONVERGED;
+  if (!std::isfinite(beta0)) {
+    last_error = "NaN or Inf in the initial residual";
+    st = CPR_ERR_NAN;
+  } else if (beta0 == 0.0) {
+    st = CPR_OK;
+    rel = 0.0;
+    est = 0.0;
+  } else {
+    for (int cycle = 0; cycle < prm.max_restarts; ++cycle) {
+      cycles = cycle;
+      // v_1 = r / ||r||, g = ||r|| e_1 (start_cycle already ran for this r)
+      launch_scale_div(N, r, hnorm, V, stream);
+      int k = 0;
+      bool bad = false;
+      for (int j = 0; j < m; ++j) {
+        double* vj = V + j * ld;
+        double* w = V + (j + 1) * ld;
+        pc->apply(vj, Zj(j), stream);
+        if (prof.on()) prof.begin(CPR_KSTAT_SPMV, stream);
+        if (f32)
+          launch_bsr_spmv<double, float>(outer.view(), static_cast<const float*>(Zj(j)), nullptr, w, stream);
+        else
+          launch_bsr_spmv<double, double>(outer.view(), static_cast<const double*>(Zj(j)), nullptr, w, stream);
+        if (prof.on())
+          prof.end(CPR_KSTAT_SPMV, stream,
+                   9.0 * nnz_b * 8 + 4.0 * nnz_b + 4.0 * (n_b + 1) + 3.0 * n_b * ((f32 ? 4 : 8) + 8));
+        launch_multidot(N, w, V, ld, 0, j + 1, partial, stream);
+        double* Hj = H + static_cast<int64_t>(j) * (m + 1);
+        launch_reduce_partials(partial, grid, j + 1, Hj, stream);
+        launch_axpy_norm(N, w, V, ld, 0, j + 1, Hj, norm_partial, stream);
+        launch_givens(m, j, norm_partial, grid, H, cs, sn, g, hnorm, report_d, stream);
+        sync_report();
+        ++its;
+        k = j + 1;
+        est = report_h[0] / beta0;
+        const double hn = report_h[1];
+        if (!std::isfinite(est) || !std::isfinite(hn)) {
+          bad = true;
+          break;
+        }
+        if (hn == 0.0) break;  // happy breakdown
+        launch_scale_div(N, w, hnorm, w, stream);
+        if (est < tol) break;
+      }
+      if (bad) {
+        last_error = "NaN or Inf during the Arnoldi process";
+        st = CPR_ERR_NAN;
+        break;
+      }
+      launch_backsolve(m, k, H, g, y, stream);
+      if (f32)
+        launch_update_x<float>(N, x, static_cast<const float*>(Z), ld, k, y, stream);
+      else
+        launch_update_x<double>(N, x, static_cast<const double*>(Z), ld, k, y, stream);
+      outer_spmv_resid(x, b, r);
+      launch_norm_partial(N, r, norm_partial, stream);
+      launch_start_cycle(m, norm_partial, grid, g, hnorm, report_d, stream);
+      sync_report();
+      rel = report_h[0] / beta0;
+      relb = bnorm > 0.0 ? report_h[0] / bnorm : 0.0;
+      if (!std::isfinite(rel)) {
+        last_error = "NaN or Inf in the true residual";
+        st = CPR_ERR_NAN;
+        break;
+      }
+      if (rel < tol) {
+        st = CPR_OK;
+        break;
+      }
+    }
+  }
+  HIPCHK(hipStreamSynchronize(stream));
+  if (prof.on()) prof.collect();
+  const double solve_ms = now_ms() - t0;
+
+  it_prev = its;
+  if (fresh) it_ref = its;
+
+  if (info) {
+    info->iterations = its;
+    info->restarts = cycles;
+    info->rebuilt = rebuild ? 1 : 0;
+    info->n_levels = pc->n_levels();
+    info->relres_true = relb;
+    info->relres_est = est;
+    info->setup_ms = setup_ms;
+    info->solve_ms = solve_ms;
+  }
+  if (st == CPR_NOT_CONVERGED) last_error = "not converged within max_restarts";
+  return st;
+}

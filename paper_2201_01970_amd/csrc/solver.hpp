@@ -1,0 +1,176 @@
+// The solver handle: SETUP (host greedy steps + device data), the CPR apply,
+// the pressure V-cycle and the FP64 flexible GMRES with the adaptive-setup rule.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/cpr.h"
+#include "../../include/cpr_inspect.h"
+#include "device.hpp"
+#include "host_setup.hpp"
+
+namespace cpr {
+
+struct Error : std::runtime_error {
+  cpr_status status;
+  Error(cpr_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+void hip_check(hipError_t e, const char* what, const char* file, int line);
+#define HIPCHK(x) ::cpr::hip_check((x), #x, __FILE__, __LINE__)
+
+// Owns a list of device allocations.
+class Arena {
+ public:
+  ~Arena() { release(); }
+  template <typename T>
+  T* alloc(int64_t n) {
+    if (n <= 0) n = 1;
+    void* p = nullptr;
+    const size_t bytes = static_cast<size_t>(n) * sizeof(T);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(CPR_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    ptrs_.push_back(p);
+    bytes_ += static_cast<int64_t>(bytes);
+    return static_cast<T*>(p);
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& v) {
+    T* p = alloc<T>(static_cast<int64_t>(v.size()));
+    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+  }
+  void release() {
+    for (void* p : ptrs_) (void)hipFree(p);
+    ptrs_.clear();
+    bytes_ = 0;
+  }
+  int64_t bytes() const { return bytes_; }
+
+ private:
+  std::vector<void*> ptrs_;
+  int64_t bytes_ = 0;
+};
+
+template <typename T>
+struct DevSell {
+  int32_t n_rows = 0;
+  int64_t slots = 0;
+  int32_t* slice_ptr = nullptr;
+  int32_t* col = nullptr;
+  T* val = nullptr;
+  SellView<T> view() const { return SellView<T>{n_rows, slice_ptr, col, val}; }
+};
+
+// Host products of SETUP for one AMG level (kept for inspection).
+struct HostLevel {
+  HostCsr A;
+  std::vector<uint8_t> mask;  // bit 1: RS strength, bit 2: eq. (strong-matrix)
+  std::vector<int32_t> colour;
+  int32_t n_colours = 0;
+  std::vector<int8_t> cf;
+  HostCsr P;
+  std::vector<int32_t> perm;  // device row p -> level row perm[p]
+  std::vector<int32_t> coff;  // colour offsets in device order
+};
+
+// Event timing of kernel classes.
+class Profiler : public LaunchTimer {
+ public:
+  ~Profiler() override;
+  void enable(bool on);
+  bool on() const { return on_; }
+  void begin(int kind, hipStream_t s) override;
+  void end(int kind, hipStream_t s, double bytes) override;
+  void collect();  // after the stream has drained
+  int64_t launches[CPR_KSTAT_COUNT] = {0};
+  double total_ms[CPR_KSTAT_COUNT] = {0};
+  double bytes[CPR_KSTAT_COUNT] = {0};
+
+ private:
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  hipEvent_t get_event();
+  bool on_ = false;
+  std::vector<Rec> pending_;
+  std::vector<hipEvent_t> free_;
+  hipEvent_t open_ev_[CPR_KSTAT_COUNT] = {};
+};
+
+class PrecondBase {
+ public:
+  virtual ~PrecondBase() = default;
+  // z = B v; z is a T* of 3n (T = the preconditioner precision)
+  virtual void apply(const double* v, void* z, hipStream_t s) = 0;
+  virtual void vcycle_own(const double* r, double* e, hipStream_t s) = 0;
+  virtual void smooth_own(int level, double* x, const double* b, int sweeps, bool zero_start, hipStream_t s) = 0;
+  virtual int n_levels() const = 0;
+  virtual bool fp32() const = 0;
+  virtual int64_t bytes() const = 0;
+  LaunchTimer* timer = nullptr;
+};
+
+std::unique_ptr<PrecondBase> make_precond(bool fp32, const cpr_params& prm, int32_t n_b,
+                                          const std::vector<HostLevel>& hl,
+                                          const std::vector<double>& lu, const std::vector<int32_t>& piv,
+                                          const std::vector<int32_t>& bperm, const std::vector<int32_t>& bcoff,
+                                          const std::vector<int32_t>& h_row_ptr, const std::vector<int32_t>& h_col,
+                                          const std::vector<int32_t>& bcolour, const double* d_vals_in,
+                                          hipStream_t s);
+
+}  // namespace cpr
+
+struct cpr_handle {
+  cpr_params prm{};
+  hipStream_t stream = nullptr;  // caller's stream (NULL = default stream)
+  int device = 0;
+  int32_t n_b = 0, nnz_b = 0;
+  uint64_t phash = 0;
+  std::vector<int32_t> h_row_ptr, h_col;
+  std::vector<double> h_vals;
+  bool h_vals_valid = false;
+
+  cpr::Arena fine;  // outer matrix, input values, Krylov workspace
+  cpr::DevSell<double> outer;
+  int64_t* d_pos_outer = nullptr;
+  double* d_vals_in = nullptr;
+  int32_t* d_singular = nullptr;
+
+  std::unique_ptr<cpr::PrecondBase> pc;
+  std::vector<cpr::HostLevel> hl;
+  std::vector<int32_t> block_colour;
+  int32_t n_block_colours = 0;
+
+  // Krylov workspace (FP64 except Z in FP32 mode)
+  int m = 30;
+  double *V = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
+  double *hnorm = nullptr, *partial = nullptr, *norm_partial = nullptr, *report_d = nullptr, *r = nullptr;
+  double* hcol = nullptr;
+  void* Z = nullptr;
+  double* report_h = nullptr;  // pinned
+
+  // adaptive setup state (Algorithm "ASCPR")
+  int64_t k_solves = 0;
+  int32_t it_prev = 0, it_ref = 0;
+  bool values_changed = false;
+  double last_setup_ms = 0.0;
+
+  cpr::Profiler prof;
+  std::string last_error;
+
+  void build_precond();
+  cpr_status solve(const double* b, double* x, double tol, cpr_solve_info* info);
+  void spmv(const double* x, double* y);
+};

@@ -1,0 +1,145 @@
+"""GPU parity of every step of the solve phase against the oracle (through the C ABI).
+
+Cases: the 20x20x5 log-normal grid (2000 cells) and a 30x40x20 SPE10-like
+grid with 2.5% inactive cells (23400 cells: many 64-row slices and a ragged
+last slice).  Bars:
+  * bit for bit: the BSR product, GPU strength masks, colours, C/F split,
+    interpolation weights, Galerkin matrices and the PGS-SCM sweeps (every sum
+    runs in the oracle's order without FMA contraction);
+  * 1e-12 relative: the V-cycle and CPR apply (the coarsest LU is factored by
+    a different routine than the oracle's LAPACK call);
+  * FP64 solve: same iteration count, iterate within 1e-10 relative;
+  * FP32 preconditioner: true relres < tol, iterations within 10%.
+"""
+import numpy as np
+import pytest
+
+from oracle import amg, cpr, fgmres, strength
+from oracle.sparse import Csr
+from workloads import blackoil as bo
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+CASES = {
+    "small": lambda: (bo.case_small(), 1001),
+    "mid": lambda: (bo.case_spe10_like(seed=1110, shape=(30, 40, 20)), 1111),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def setup_pair(request):
+    from paper_2201_01970_amd import Params, Solver
+
+    case, rseed = CASES[request.param]()
+    print(f"[case {request.param}] n_b={case.n_b} nnz_b={case.nnz_b}", flush=True)
+    A = cpr.Bsr.from_case(case)
+    B = cpr.setup(A)
+    b = bo.rhs(case.ndof, rseed)
+    S = Solver(_dev(case.row_ptr), _dev(case.col), _dev(case.vals.reshape(-1)), Params())
+    yield request.param, case, A, B, b, S
+    S.close()
+
+
+def test_spmv_bit_exact(setup_pair):
+    name, case, A, B, b, S = setup_pair
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(case.ndof)
+    y = S.spmv(_dev(x)).cpu().numpy()
+    want = cpr.bsr_matvec(A, x)
+    assert np.array_equal(y, want)
+
+
+def test_hierarchy_bit_exact(setup_pair):
+    name, case, A, B, b, S = setup_pair
+    H = B.amg
+    info0 = S.level_info(0)
+    assert info0["n_levels"] == H.n_levels
+    for l, lev in enumerate(H.levels):
+        got = S.level_arrays(l)
+        assert np.array_equal(got["row_ptr"], lev.A.indptr)
+        assert np.array_equal(got["col"], lev.A.indices)
+        assert np.array_equal(got["val"], lev.A.data)
+        if l + 1 < H.n_levels:
+            rs_mask, _ = strength.rs_strength(lev.A, 0.25)
+            c_mask, _ = strength.color_strength(lev.A, 0.05)
+            assert np.array_equal(got["rs_strong"], rs_mask)
+            assert np.array_equal(got["color_strong"], c_mask)
+            assert np.array_equal(got["cf"], lev.cf)
+            from oracle import coloring
+            assert np.array_equal(got["colour"], coloring.colour_array(lev.A.n_rows, lev.colours))
+            p_ptr, p_col, p_val = S.level_interp(l)
+            assert np.array_equal(p_ptr, lev.P.indptr)
+            assert np.array_equal(p_col, lev.P.indices)
+            assert np.array_equal(p_val, lev.P.data)
+    from oracle import coloring
+    assert np.array_equal(S.block_colours(), coloring.colour_array(A.n_b, B.block_colours))
+
+
+def test_smoother_bit_exact(setup_pair):
+    name, case, A, B, b, S = setup_pair
+    H = B.amg
+    rng = np.random.default_rng(6)
+    for l in range(H.n_levels - 1):
+        lev = H.levels[l]
+        bb = rng.standard_normal(lev.A.n_rows)
+        x0 = rng.standard_normal(lev.A.n_rows)
+        # two sweeps from an arbitrary start
+        want = x0.copy()
+        for _ in range(2):
+            amg.colour_sweep(lev.A, lev.colours, want, bb)
+        got = S.smooth(l, _dev(x0.copy()), _dev(bb), sweeps=2, zero_start=False).cpu().numpy()
+        assert np.array_equal(got, want), l
+        # two sweeps from zero (first sweep uses the zero-start kernel)
+        want = np.zeros_like(bb)
+        for _ in range(2):
+            amg.colour_sweep(lev.A, lev.colours, want, bb)
+        got = S.smooth(l, _dev(np.zeros_like(bb)), _dev(bb), sweeps=2, zero_start=True).cpu().numpy()
+        assert np.array_equal(got, want), l
+
+
+def test_vcycle_and_cpr_apply(setup_pair):
+    name, case, A, B, b, S = setup_pair
+    rng = np.random.default_rng(7)
+    r = rng.standard_normal(A.n_b)
+    want = amg.vcycle(B.amg, r)
+    got = S.vcycle(_dev(r)).cpu().numpy()
+    assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+    v = rng.standard_normal(case.ndof)
+    want = B.apply(v)
+    got = S.precond(_dev(v)).cpu().numpy()
+    assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+
+
+def test_fp64_solve_matches_oracle(setup_pair):
+    name, case, A, B, b, S = setup_pair
+    res = fgmres.fgmres(lambda v: cpr.bsr_matvec(A, v), B.apply, b, tol=1e-6)
+    x, info = S.solve(_dev(b), tol=1e-6)
+    x = x.cpu().numpy()
+    print(f"[{name}] gpu its={info['iterations']} oracle its={res.iterations} relres={info['relres_true']:.3e}")
+    assert info["iterations"] == res.iterations
+    assert np.linalg.norm(x - res.x) <= 1e-10 * np.linalg.norm(res.x)
+    assert info["relres_true"] < 1e-6
+    r = b - A.to_dense() @ x if A.n_b <= 3000 else b - cpr.bsr_matvec(A, x)
+    assert abs(np.linalg.norm(r) / np.linalg.norm(b) - info["relres_true"]) < 1e-9
+
+
+def test_fp32_preconditioner_solve(setup_pair):
+    from paper_2201_01970_amd import Params, Solver
+
+    name, case, A, B, b, S = setup_pair
+    S32 = Solver(_dev(case.row_ptr), _dev(case.col), _dev(case.vals.reshape(-1)), Params(precond_fp32=True))
+    x, info = S32.solve(_dev(b), tol=1e-6)
+    _, info64 = S.solve(_dev(b), tol=1e-6)
+    x = x.cpu().numpy()
+    rel = np.linalg.norm(b - cpr.bsr_matvec(A, x)) / np.linalg.norm(b)
+    print(f"[{name}] fp32 its={info['iterations']} fp64 its={info64['iterations']} relres={rel:.3e}")
+    assert rel < 1e-6
+    assert abs(info["iterations"] - info64["iterations"]) <= max(1, 0.1 * info64["iterations"])
+    S32.close()

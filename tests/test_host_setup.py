@@ -1,0 +1,126 @@
+"""The library's host-side SETUP routines against the oracle, bit for bit (CPU).
+
+The strength patterns fed to both sides come from the oracle; the library's
+VerticesGrouping, RS split, interpolation and Galerkin product must then give
+exactly the oracle's colours, C/F split, weights and coarse matrix.  Also
+checks that the shared library exports every symbol the headers declare.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import coloring, rs, strength
+from oracle.cpr import Bsr, pressure_matrix
+from oracle.sparse import pattern_lists
+from workloads import blackoil as bo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2201_01970_amd", "libcpr_mi355x.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="HIP library not built")
+
+
+def _declared_symbols():
+    names = set()
+    for h in ("cpr.h", "cpr_inspect.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(cpr_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+
+    lib = ctypes.CDLL(LIB)
+    names = _declared_symbols()
+    assert len(names) >= 20
+    for name in sorted(names):
+        assert hasattr(lib, name), name
+    from paper_2201_01970_amd import _capi
+
+    assert set(_capi.SIGNATURES) == names
+
+
+def _levels_of(case_shape, seed, theta_rs=0.25):
+    """A chain of oracle levels (A, rs mask, S lists, cf, P) of a generated case."""
+    from oracle import amg
+
+    case = bo.case_spe10_like(seed=seed, shape=case_shape, inactive_frac=0.05)
+    H = amg.build_hierarchy(pressure_matrix(Bsr.from_case(case)), amg.AmgParams(theta_rs=theta_rs))
+    return H
+
+
+def _csr32(A):
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data
+
+
+def test_grouping_bit_exact():
+    from paper_2201_01970_amd import host_grouping
+
+    H = _levels_of((14, 12, 6), 51)
+    for lev in H.levels[:-1]:
+        for theta in (0.0, 0.05, 0.3):
+            _, (ip, ix) = strength.color_strength(lev.A, theta)
+            want = coloring.colour_array(lev.A.n_rows, coloring.vertices_grouping(lev.A.n_rows,
+                                                                                   pattern_lists(ip, ix)))
+            got, nc = host_grouping(ip, ix)
+            assert nc == want.max() + 1
+            assert np.array_equal(got, want)
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        n = int(rng.integers(1, 40))
+        d = (rng.uniform(size=(n, n)) < rng.uniform(0.02, 0.4))
+        np.fill_diagonal(d, False)
+        S = [list(np.nonzero(d[i])[0]) for i in range(n)]
+        ip = np.concatenate([[0], np.cumsum([len(s) for s in S])])
+        ix = np.array([j for s in S for j in s], dtype=np.int64)
+        want = coloring.colour_array(n, coloring.vertices_grouping(n, S))
+        got, _ = host_grouping(ip, ix)
+        assert np.array_equal(got, want)
+
+
+def test_rs_split_interp_galerkin_bit_exact():
+    from paper_2201_01970_amd import host_galerkin, host_interpolation, host_rs_split
+
+    for shape, seed in (((14, 12, 6), 52), ((20, 9, 7), 53)):
+        H = _levels_of(shape, seed)
+        assert H.n_levels >= 3
+        for lev in H.levels[:-1]:
+            A = lev.A
+            mask, (ip, ix) = strength.rs_strength(A, 0.25)
+            cf = host_rs_split(ip, ix)
+            assert np.array_equal(cf, lev.cf)
+            p_ptr, p_col, p_val, nc = host_interpolation(*_csr32(A), mask.astype(np.uint8), cf)
+            assert nc == lev.P.n_cols
+            assert np.array_equal(p_ptr, lev.P.indptr)
+            assert np.array_equal(p_col, lev.P.indices)
+            assert np.array_equal(p_val, lev.P.data)  # bit for bit
+            Ac_ptr, Ac_col, Ac_val = host_galerkin(*_csr32(A), p_ptr, p_col, p_val, nc)
+            nxt = H.levels[H.levels.index(lev) + 1].A
+            assert np.array_equal(Ac_ptr, nxt.indptr)
+            assert np.array_equal(Ac_col, nxt.indices)
+            assert np.array_equal(Ac_val, nxt.data)
+
+
+def test_rs_split_random_graphs_bit_exact():
+    from paper_2201_01970_amd import host_rs_split
+
+    rng = np.random.default_rng(4)
+    for _ in range(300):
+        n = int(rng.integers(1, 50))
+        d = rng.uniform(size=(n, n)) < rng.uniform(0.02, 0.3)
+        np.fill_diagonal(d, False)
+        S = [list(np.nonzero(d[i])[0]) for i in range(n)]
+        ST = [[] for _ in range(n)]
+        for i in range(n):
+            for j in S[i]:
+                ST[j].append(i)
+        want = rs.rs_split(n, S, ST)
+        ip = np.concatenate([[0], np.cumsum([len(s) for s in S])])
+        ix = np.array([j for s in S for j in s], dtype=np.int64)
+        got = host_rs_split(ip, ix)
+        assert np.array_equal(got, want)
