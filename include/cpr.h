@@ -78,6 +78,7 @@ typedef struct {
                              2: relative rule, reuse iff It^(k-1) <= reuse_factor*It_ref [2] */
   int32_t mu;             /* threshold of reuse_mode 1 [20] */
   double reuse_factor;    /* factor of reuse_mode 2 [1.3] */
+  int32_t use_graphs;     /* 1: replay each FGMRES step as one captured HIP graph [1] */
 } cpr_params;
 
 typedef struct {

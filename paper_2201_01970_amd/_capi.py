@@ -59,6 +59,7 @@ class cpr_params(C.Structure):
         ("reuse_mode", C.c_int32),
         ("mu", C.c_int32),
         ("reuse_factor", C.c_double),
+        ("use_graphs", C.c_int32),
     ]
 
 

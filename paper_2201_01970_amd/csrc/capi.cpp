@@ -136,6 +136,7 @@ void cpr_params_default(cpr_params* p) {
   p->reuse_mode = 2;
   p->mu = 20;
   p->reuse_factor = 1.3;
+  p->use_graphs = 1;
 }
 
 cpr_status cpr_setup(const cpr_bsr* A, const cpr_params* p, void* hip_stream, cpr_handle** out) {
@@ -227,6 +228,8 @@ cpr_status cpr_set_stream(cpr_handle* h, void* hip_stream) {
 void cpr_destroy(cpr_handle* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
+  h->drop_graphs();
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   h->pc.reset();
   h->fine.release();
   if (h->report_h) (void)hipHostFree(h->report_h);

@@ -31,6 +31,17 @@ struct SellView {
   const T* val = nullptr;
 };
 
+// An AMG level matrix (or P, R): group == 1 -> SELL-64 (ptr = slice_ptr),
+// group in {16, 32, 64} -> CSR read by `group` lanes per row (ptr = row_ptr).
+template <typename T>
+struct MatView {
+  int32_t n_rows = 0;
+  int32_t group = 1;
+  const int32_t* ptr = nullptr;
+  const int32_t* col = nullptr;
+  const T* val = nullptr;
+};
+
 // Kernel classes whose launches can be timed with HIP events.
 struct LaunchTimer {
   virtual ~LaunchTimer() = default;
@@ -71,25 +82,25 @@ template <typename T>
 void launch_bsr_values_to_sell(int64_t nnzb, const double* vals, const int64_t* pos, T* sell_val,
                                hipStream_t s);
 
-// ---- AMG level kernels (CSR in SELL-64, rows in colour order) ----
+// ---- AMG level kernels (rows in colour order) ----
 // One colour [lo, hi): x_i = (b_i - sum_{j != i} a_ij xt_j) / a_ii, where xt_j is
 // s_in[j] for j in [lo, hi) and x[j] otherwise; zero_start: x = 0 on entry, so
 // only j < lo contribute.  Writes x[i] and s_out[i].
 template <typename T>
-void launch_gs_colour(const SellView<T>& A, const T* diag, int32_t lo, int32_t hi, const T* b, T* x,
+void launch_gs_colour(const MatView<T>& A, const T* diag, int32_t lo, int32_t hi, const T* b, T* x,
                       const T* s_in, T* s_out, bool zero_start, hipStream_t s);
 
 // r = b - A x (stored order, diagonal included)
 template <typename T>
-void launch_csr_residual(const SellView<T>& A, const T* b, const T* x, T* r, hipStream_t s);
+void launch_csr_residual(const MatView<T>& A, const T* b, const T* x, T* r, hipStream_t s);
 
 // y = A x (sum from 0 in stored order)
 template <typename T>
-void launch_csr_spmv(const SellView<T>& A, const T* x, T* y, hipStream_t s);
+void launch_csr_spmv(const MatView<T>& A, const T* x, T* y, hipStream_t s);
 
 // x_i = x_i + (sum_J p_iJ e_J); snap[i] = x_i
 template <typename T>
-void launch_prolong_add(const SellView<T>& P, const T* e, T* x, T* snap, hipStream_t s);
+void launch_prolong_add(const MatView<T>& P, const T* e, T* x, T* snap, hipStream_t s);
 
 // Dense LU solve on one workgroup: x = A^{-1} b with FP64 factors.
 template <typename T>

@@ -1,157 +1,275 @@
 // Pressure-AMG kernels: the PGS-SCM colour sweep (Algorithm "PGS-SCM"),
-// residual, restriction, prolongation and the dense coarsest solve.  Level
-// matrices are SELL-64 with rows in colour order; each lane sums its own row
-// in stored order, so results match a sequential row loop bit for bit.
+// residual, restriction, prolongation and the dense coarsest solve.
+//
+// Two storage forms, chosen per matrix at SETUP from its row lengths:
+//  * SELL-64, one lane per row (short rows: the finest level, P, R).  Slots
+//    are fetched kUnroll at a time so the gathers of a row overlap.
+//  * CSR with a group of 16, 32 or 64 lanes per row (long rows of the
+//    Galerkin levels).  Each lane fetches one stored entry of a chunk (two
+//    chunks in flight) and forms its product; the group then adds the
+//    products in stored order, broadcast one lane at a time (through the
+//    scalar unit when the group is the whole wavefront).
+// Either way every row is accumulated exactly as a sequential loop over its
+// stored entries would (products rounded, then added in order), so results
+// match a sequential implementation bit for bit.  Entries that do not
+// contribute are replaced by a zero product, which leaves the sum unchanged.
 #include "kernels_common.hpp"
 
 namespace cpr {
 
-// One colour [lo, hi).  Same-colour neighbours are read from the snapshot s_in
-// (their values before this colour started), all others from x (earlier
-// colours already updated in this sweep).  ZERO: x == 0 on entry, so only the
-// earlier colours (j < lo) contribute.
+constexpr int kUnroll = 8;
+constexpr int kChunks = 2;  // chunks of a long row whose loads are issued together
+
+// ------------------------------------------------------------------ helpers
+// Row q of a SELL matrix: call f(col, val) for each stored entry in order,
+// with the loads of kUnroll consecutive slots issued together.
+template <typename T, typename F>
+__device__ __forceinline__ void sell_row(int32_t q, const int32_t* __restrict__ slice_ptr,
+                                         const int32_t* __restrict__ col, const T* __restrict__ val, F&& f) {
+  const int32_t slice = q >> 6, lane = q & 63;
+  const int32_t t0 = slice_ptr[slice], t1 = slice_ptr[slice + 1];
+  for (int32_t t = t0; t < t1; t += kUnroll) {
+    int32_t c[kUnroll];
+    T a[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t e = (int64_t)(t + u) * kWave + lane;
+      c[u] = (t + u < t1) ? col[e] : kPadCol;
+      a[u] = (c[u] >= 0) ? val[e] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) f(c[u], a[u]);
+  }
+}
+
+// Value of lane k (compile-time) of the wavefront, read through the scalar unit.
+__device__ __forceinline__ float lane_value(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ __forceinline__ double lane_value(double v, int k) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffffll), k);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), k);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Ordered sum over one chunk of a group: s = s (op) p_0 (op) p_1 ... in lane order.
+template <typename T, int G, bool SUB>
+__device__ __forceinline__ T group_ordered(T s, T p) {
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    const T v = (G == kWave) ? lane_value(p, k) : __shfl(p, k, G);
+    s = SUB ? (s - v) : (s + v);
+  }
+  return s;
+}
+
+// ------------------------------------------------------------------ colour sweep
+// One colour [lo, hi): x_i = (b_i - sum_{j != i} a_ij xt_j) / a_ii with xt_j =
+// s_in[j] for j in [lo, hi) (the colour's values before this colour started)
+// and x[j] otherwise; ZERO: x == 0 on entry, so only j < lo contribute.
 template <typename T, bool ZERO>
-__global__ __launch_bounds__(kBlock) void k_gs_colour(int32_t lo, int32_t hi, const int32_t* __restrict__ slice_ptr,
-                                                      const int32_t* __restrict__ col, const T* __restrict__ val,
-                                                      const T* __restrict__ diag, const T* __restrict__ b,
-                                                      T* __restrict__ x, const T* __restrict__ s_in,
-                                                      T* __restrict__ s_out) {
+__device__ __forceinline__ T gs_value(int32_t q, int32_t c, int32_t lo, int32_t hi, const T* __restrict__ x,
+                                      const T* __restrict__ s_in, bool& use) {
+  use = c >= 0 && c != q && (!ZERO || c < lo);
+  if (!use) return (T)0;
+  if (ZERO) return x[c];
+  return (c >= lo && c < hi) ? s_in[c] : x[c];
+}
+
+template <typename T, bool ZERO>
+__global__ __launch_bounds__(kBlock) void k_gs_sell(int32_t lo, int32_t hi, const int32_t* __restrict__ slice_ptr,
+                                                    const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                    const T* __restrict__ diag, const T* __restrict__ b,
+                                                    T* __restrict__ x, const T* __restrict__ s_in,
+                                                    T* __restrict__ s_out) {
   const int32_t base = lo & ~63;
   const int32_t q = base + xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (q < lo || q >= hi) return;
-  const int32_t slice = q >> 6, lane = q & 63;
   T s = b[q];
-  const int32_t t0 = slice_ptr[slice], t1 = slice_ptr[slice + 1];
-  for (int32_t t = t0; t < t1; ++t) {
-    const int64_t e = (int64_t)t * kWave + lane;
-    const int32_t c = col[e];
-    if (c < 0) break;
-    if (c == q) continue;
-    T xv;
-    if (ZERO) {
-      if (c >= lo) continue;
-      xv = x[c];
-    } else {
-      xv = (c >= lo && c < hi) ? s_in[c] : x[c];
-    }
-    s = s - val[e] * xv;
-  }
+  sell_row<T>(q, slice_ptr, col, val, [&](int32_t c, T a) {
+    bool use;
+    const T xv = gs_value<T, ZERO>(q, c, lo, hi, x, s_in, use);
+    const T prod = use ? a * xv : (T)0;
+    s = s - prod;
+  });
   const T xn = s / diag[q];
   x[q] = xn;
   s_out[q] = xn;
 }
 
+template <typename T, int G, bool ZERO>
+__global__ __launch_bounds__(kBlock) void k_gs_grp(int32_t lo, int32_t hi, const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                   const T* __restrict__ diag, const T* __restrict__ b,
+                                                   T* __restrict__ x, const T* __restrict__ s_in,
+                                                   T* __restrict__ s_out) {
+  const int32_t g = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  const int32_t q = lo + g;
+  if (q >= hi) return;
+  T s = b[q];
+  const int32_t p0 = rp[q], p1 = rp[q + 1];
+  for (int32_t p = p0; p < p1; p += G * kChunks) {
+    int32_t c[kChunks];
+    T a[kChunks], prod[kChunks];
+#pragma unroll
+    for (int u = 0; u < kChunks; ++u) {
+      const int32_t e = p + u * G + lane;
+      c[u] = (e < p1) ? col[e] : kPadCol;
+      a[u] = (e < p1) ? val[e] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < kChunks; ++u) {
+      bool use;
+      const T xv = gs_value<T, ZERO>(q, c[u], lo, hi, x, s_in, use);
+      prod[u] = use ? a[u] * xv : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < kChunks; ++u) s = group_ordered<T, G, true>(s, prod[u]);
+  }
+  if (lane == 0) {
+    const T xn = s / diag[q];
+    x[q] = xn;
+    s_out[q] = xn;
+  }
+}
+
 template <typename T>
-void launch_gs_colour(const SellView<T>& A, const T* diag, int32_t lo, int32_t hi, const T* b, T* x, const T* s_in,
+void launch_gs_colour(const MatView<T>& A, const T* diag, int32_t lo, int32_t hi, const T* b, T* x, const T* s_in,
                       T* s_out, bool zero_start, hipStream_t s) {
   if (hi <= lo) return;
-  const int32_t base = lo & ~63;
-  const int grid = div_up(hi - base, kBlock);
-  if (zero_start)
-    hipLaunchKernelGGL((k_gs_colour<T, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.slice_ptr, A.col, A.val,
+  if (A.group == 1) {
+    const int32_t base = lo & ~63;
+    const int grid = div_up(hi - base, kBlock);
+    if (zero_start)
+      hipLaunchKernelGGL((k_gs_sell<T, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag, b,
+                         x, s_in, s_out);
+    else
+      hipLaunchKernelGGL((k_gs_sell<T, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag,
+                         b, x, s_in, s_out);
+  } else {
+    const int grid = div_up((int64_t)(hi - lo) * A.group, kBlock);
+#define CPR_GS_GRP(G)                                                                                         \
+  if (zero_start)                                                                                             \
+    hipLaunchKernelGGL((k_gs_grp<T, G, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag, \
+                       b, x, s_in, s_out);                                                                     \
+  else                                                                                                        \
+    hipLaunchKernelGGL((k_gs_grp<T, G, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val,     \
                        diag, b, x, s_in, s_out);
-  else
-    hipLaunchKernelGGL((k_gs_colour<T, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.slice_ptr, A.col, A.val,
-                       diag, b, x, s_in, s_out);
+    if (A.group == 16) {
+      CPR_GS_GRP(16)
+    } else if (A.group == 32) {
+      CPR_GS_GRP(32)
+    } else {
+      CPR_GS_GRP(64)
+    }
+#undef CPR_GS_GRP
+  }
   CPR_LAUNCH_CHECK();
 }
-template void launch_gs_colour<double>(const SellView<double>&, const double*, int32_t, int32_t, const double*,
+template void launch_gs_colour<double>(const MatView<double>&, const double*, int32_t, int32_t, const double*,
                                        double*, const double*, double*, bool, hipStream_t);
-template void launch_gs_colour<float>(const SellView<float>&, const float*, int32_t, int32_t, const float*, float*,
+template void launch_gs_colour<float>(const MatView<float>&, const float*, int32_t, int32_t, const float*, float*,
                                       const float*, float*, bool, hipStream_t);
 
-// r_i = b_i - a_i1 x_1 - a_i2 x_2 - ... (stored order, diagonal included)
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_csr_residual(int32_t n, const int32_t* __restrict__ slice_ptr,
-                                                         const int32_t* __restrict__ col, const T* __restrict__ val,
-                                                         const T* __restrict__ b, const T* __restrict__ x,
-                                                         T* __restrict__ r) {
+// ------------------------------------------------------------------ row products
+// MODE 0: y = b - A x (residual; products subtracted from b in stored order)
+// MODE 1: y = A x (sum from 0 in stored order)
+// MODE 2: y = y + (A x), snap = y (prolongation add; the sum from 0 first)
+template <typename T, int MODE>
+__device__ __forceinline__ void finish_row(int32_t q, T acc, const T* __restrict__ b, T* __restrict__ y,
+                                           T* __restrict__ snap) {
+  if (MODE == 2) {
+    const T yn = y[q] + acc;
+    y[q] = yn;
+    snap[q] = yn;
+  } else {
+    y[q] = acc;
+  }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_rows_sell(int32_t n, const int32_t* __restrict__ slice_ptr,
+                                                      const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                      const T* __restrict__ b, const T* __restrict__ x,
+                                                      T* __restrict__ y, T* __restrict__ snap) {
   const int32_t q = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (q >= n) return;
-  const int32_t slice = q >> 6, lane = q & 63;
-  T s = b[q];
-  const int32_t t0 = slice_ptr[slice], t1 = slice_ptr[slice + 1];
-  for (int32_t t = t0; t < t1; ++t) {
-    const int64_t e = (int64_t)t * kWave + lane;
-    const int32_t c = col[e];
-    if (c < 0) break;
-    s = s - val[e] * x[c];
-  }
-  r[q] = s;
+  T acc = (MODE == 0) ? b[q] : (T)0;
+  sell_row<T>(q, slice_ptr, col, val, [&](int32_t c, T a) {
+    const T prod = (c >= 0) ? a * x[c] : (T)0;
+    acc = (MODE == 0) ? (acc - prod) : (acc + prod);
+  });
+  finish_row<T, MODE>(q, acc, b, y, snap);
 }
 
-template <typename T>
-void launch_csr_residual(const SellView<T>& A, const T* b, const T* x, T* r, hipStream_t s) {
-  if (A.n_rows == 0) return;
-  hipLaunchKernelGGL((k_csr_residual<T>), dim3(div_up(A.n_rows, kBlock)), dim3(kBlock), 0, s, A.n_rows, A.slice_ptr,
-                     A.col, A.val, b, x, r);
-  CPR_LAUNCH_CHECK();
-}
-template void launch_csr_residual<double>(const SellView<double>&, const double*, const double*, double*,
-                                          hipStream_t);
-template void launch_csr_residual<float>(const SellView<float>&, const float*, const float*, float*, hipStream_t);
-
-// y_i = 0 + a_i1 x_1 + a_i2 x_2 + ... (stored order)
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_csr_spmv(int32_t n, const int32_t* __restrict__ slice_ptr,
+template <typename T, int G, int MODE>
+__global__ __launch_bounds__(kBlock) void k_rows_grp(int32_t n, const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ col, const T* __restrict__ val,
-                                                     const T* __restrict__ x, T* __restrict__ y) {
-  const int32_t q = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+                                                     const T* __restrict__ b, const T* __restrict__ x,
+                                                     T* __restrict__ y, T* __restrict__ snap) {
+  const int32_t q = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
   if (q >= n) return;
-  const int32_t slice = q >> 6, lane = q & 63;
-  T s = (T)0;
-  const int32_t t0 = slice_ptr[slice], t1 = slice_ptr[slice + 1];
-  for (int32_t t = t0; t < t1; ++t) {
-    const int64_t e = (int64_t)t * kWave + lane;
-    const int32_t c = col[e];
-    if (c < 0) break;
-    s = s + val[e] * x[c];
+  T acc = (MODE == 0) ? b[q] : (T)0;
+  const int32_t p0 = rp[q], p1 = rp[q + 1];
+  for (int32_t p = p0; p < p1; p += G * kChunks) {
+    int32_t c[kChunks];
+    T a[kChunks], prod[kChunks];
+#pragma unroll
+    for (int u = 0; u < kChunks; ++u) {
+      const int32_t e = p + u * G + lane;
+      c[u] = (e < p1) ? col[e] : kPadCol;
+      a[u] = (e < p1) ? val[e] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < kChunks; ++u) prod[u] = (c[u] >= 0) ? a[u] * x[c[u]] : (T)0;
+#pragma unroll
+    for (int u = 0; u < kChunks; ++u) acc = group_ordered<T, G, MODE == 0>(acc, prod[u]);
   }
-  y[q] = s;
+  if (lane == 0) finish_row<T, MODE>(q, acc, b, y, snap);
 }
 
-template <typename T>
-void launch_csr_spmv(const SellView<T>& A, const T* x, T* y, hipStream_t s) {
+template <typename T, int MODE>
+void launch_rows(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, hipStream_t s) {
   if (A.n_rows == 0) return;
-  hipLaunchKernelGGL((k_csr_spmv<T>), dim3(div_up(A.n_rows, kBlock)), dim3(kBlock), 0, s, A.n_rows, A.slice_ptr,
-                     A.col, A.val, x, y);
+  if (A.group == 1)
+    hipLaunchKernelGGL((k_rows_sell<T, MODE>), dim3(div_up(A.n_rows, kBlock)), dim3(kBlock), 0, s, A.n_rows, A.ptr,
+                       A.col, A.val, b, x, y, snap);
+  else if (A.group == 16)
+    hipLaunchKernelGGL((k_rows_grp<T, 16, MODE>), dim3(div_up((int64_t)A.n_rows * 16, kBlock)), dim3(kBlock), 0, s,
+                       A.n_rows, A.ptr, A.col, A.val, b, x, y, snap);
+  else if (A.group == 32)
+    hipLaunchKernelGGL((k_rows_grp<T, 32, MODE>), dim3(div_up((int64_t)A.n_rows * 32, kBlock)), dim3(kBlock), 0, s,
+                       A.n_rows, A.ptr, A.col, A.val, b, x, y, snap);
+  else
+    hipLaunchKernelGGL((k_rows_grp<T, 64, MODE>), dim3(div_up((int64_t)A.n_rows * 64, kBlock)), dim3(kBlock), 0, s,
+                       A.n_rows, A.ptr, A.col, A.val, b, x, y, snap);
   CPR_LAUNCH_CHECK();
-}
-template void launch_csr_spmv<double>(const SellView<double>&, const double*, double*, hipStream_t);
-template void launch_csr_spmv<float>(const SellView<float>&, const float*, float*, hipStream_t);
-
-// x_i = x_i + (0 + p_i1 e_1 + ...); snap_i = x_i
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong_add(int32_t n, const int32_t* __restrict__ slice_ptr,
-                                                        const int32_t* __restrict__ col, const T* __restrict__ val,
-                                                        const T* __restrict__ e, T* __restrict__ x,
-                                                        T* __restrict__ snap) {
-  const int32_t q = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (q >= n) return;
-  const int32_t slice = q >> 6, lane = q & 63;
-  T s = (T)0;
-  const int32_t t0 = slice_ptr[slice], t1 = slice_ptr[slice + 1];
-  for (int32_t t = t0; t < t1; ++t) {
-    const int64_t k = (int64_t)t * kWave + lane;
-    const int32_t c = col[k];
-    if (c < 0) break;
-    s = s + val[k] * e[c];
-  }
-  const T xn = x[q] + s;
-  x[q] = xn;
-  snap[q] = xn;
 }
 
 template <typename T>
-void launch_prolong_add(const SellView<T>& P, const T* e, T* x, T* snap, hipStream_t s) {
-  if (P.n_rows == 0) return;
-  hipLaunchKernelGGL((k_prolong_add<T>), dim3(div_up(P.n_rows, kBlock)), dim3(kBlock), 0, s, P.n_rows, P.slice_ptr,
-                     P.col, P.val, e, x, snap);
-  CPR_LAUNCH_CHECK();
+void launch_csr_residual(const MatView<T>& A, const T* b, const T* x, T* r, hipStream_t s) {
+  launch_rows<T, 0>(A, b, x, r, nullptr, s);
 }
-template void launch_prolong_add<double>(const SellView<double>&, const double*, double*, double*, hipStream_t);
-template void launch_prolong_add<float>(const SellView<float>&, const float*, float*, float*, hipStream_t);
+template <typename T>
+void launch_csr_spmv(const MatView<T>& A, const T* x, T* y, hipStream_t s) {
+  launch_rows<T, 1>(A, nullptr, x, y, nullptr, s);
+}
+template <typename T>
+void launch_prolong_add(const MatView<T>& P, const T* e, T* x, T* snap, hipStream_t s) {
+  launch_rows<T, 2>(P, nullptr, e, x, snap, s);
+}
+#define CPR_INST_ROWS(T)                                                                               \
+  template void launch_csr_residual<T>(const MatView<T>&, const T*, const T*, T*, hipStream_t);     \
+  template void launch_csr_spmv<T>(const MatView<T>&, const T*, T*, hipStream_t);                    \
+  template void launch_prolong_add<T>(const MatView<T>&, const T*, T*, T*, hipStream_t);
+CPR_INST_ROWS(double)
+CPR_INST_ROWS(float)
+#undef CPR_INST_ROWS
 
+// ------------------------------------------------------------------ coarsest solve
 // Dense LU solve in one workgroup (FP64): P A = L U with the row swaps applied
 // to b in factorisation order, unit-lower forward and upper back substitution.
 template <typename T>

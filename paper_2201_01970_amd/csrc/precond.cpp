@@ -48,15 +48,62 @@ SellHost build_sell(const HostCsr& A, const std::vector<int32_t>& order, const s
   return S;
 }
 
+// A level matrix on the device in the form its row lengths call for: SELL-64
+// (one lane per row) when rows are short, CSR read by lane groups of 16, 32 or
+// 64 when the average row holds more than kLongRow entries.
+constexpr double kLongRow = 12.0;
+
+int32_t group_for(double avg) {
+  if (avg <= 24.0) return 16;
+  if (avg <= 48.0) return 32;
+  return 64;
+}
+
 template <typename T>
-DevSell<T> upload_sell(Arena& ar, const SellHost& S) {
-  DevSell<T> D;
-  D.n_rows = S.n_rows;
-  D.slots = S.slice_ptr.empty() ? 0 : S.slice_ptr.back();
-  D.slice_ptr = ar.upload(S.slice_ptr);
-  D.col = ar.upload(S.col);
-  std::vector<T> v(S.val.begin(), S.val.end());
-  D.val = ar.upload(v);
+struct DevMat {
+  int32_t n_rows = 0;
+  int32_t group = 1;
+  int64_t stored = 0;  // stored entries including SELL padding
+  int32_t* ptr = nullptr;
+  int32_t* col = nullptr;
+  T* val = nullptr;
+  MatView<T> view() const { return MatView<T>{n_rows, group, ptr, col, val}; }
+};
+
+template <typename T>
+DevMat<T> upload_mat(Arena& ar, const HostCsr& A, const std::vector<int32_t>& order,
+                     const std::vector<int32_t>& colmap) {
+  DevMat<T> D;
+  const int32_t n = static_cast<int32_t>(order.size());
+  D.n_rows = n;
+  const double avg = n > 0 ? static_cast<double>(A.nnz()) / n : 0.0;
+  if (avg <= kLongRow) {
+    const SellHost S = build_sell(A, order, colmap);
+    D.group = 1;
+    D.stored = static_cast<int64_t>(S.col.size());
+    D.ptr = ar.upload(S.slice_ptr);
+    D.col = ar.upload(S.col);
+    std::vector<T> v(S.val.begin(), S.val.end());
+    D.val = ar.upload(v);
+    return D;
+  }
+  std::vector<int32_t> rp(n + 1, 0), col;
+  std::vector<T> val;
+  col.reserve(A.nnz());
+  val.reserve(A.nnz());
+  for (int32_t p = 0; p < n; ++p) {
+    const int32_t i = order[p];
+    for (int32_t q = A.ptr[i]; q < A.ptr[i + 1]; ++q) {
+      col.push_back(colmap.empty() ? A.col[q] : colmap[A.col[q]]);
+      val.push_back(static_cast<T>(A.val[q]));
+    }
+    rp[p + 1] = static_cast<int32_t>(col.size());
+  }
+  D.group = group_for(avg);
+  D.stored = static_cast<int64_t>(col.size());
+  D.ptr = ar.upload(rp);
+  D.col = ar.upload(col);
+  D.val = ar.upload(val);
   return D;
 }
 
@@ -76,7 +123,7 @@ class Precond final : public PrecondBase {
     int64_t nnz = 0, nnz_p = 0, nnz_r = 0;
     std::vector<int32_t> coff;
     std::vector<double> colour_bytes;  // algorithmic bytes of each colour launch
-    DevSell<T> A, P, R;
+    DevMat<T> A, P, R;
     T *diag = nullptr, *x = nullptr, *b = nullptr, *r = nullptr, *s0 = nullptr, *s1 = nullptr;
     int32_t* perm = nullptr;
   };
@@ -101,7 +148,7 @@ class Precond final : public PrecondBase {
       L.x = ar_.alloc<T>(L.n);
       L.b = ar_.alloc<T>(L.n);
       if (l + 1 < nl) {
-        L.A = upload_sell<T>(ar_, build_sell(H.A, H.perm, inv[l]));
+        L.A = upload_mat<T>(ar_, H.A, H.perm, inv[l]);
         std::vector<T> dg(L.n);
         for (int32_t p = 0; p < L.n; ++p) {
           const int32_t i = H.perm[p];
@@ -114,9 +161,9 @@ class Precond final : public PrecondBase {
         L.r = ar_.alloc<T>(L.n);
         L.s0 = ar_.alloc<T>(L.n);
         L.s1 = ar_.alloc<T>(L.n);
-        L.P = upload_sell<T>(ar_, build_sell(H.P, H.perm, inv[l + 1]));
+        L.P = upload_mat<T>(ar_, H.P, H.perm, inv[l + 1]);
         const HostCsr R = transpose(H.P);
-        L.R = upload_sell<T>(ar_, build_sell(R, hl[l + 1].perm, inv[l]));
+        L.R = upload_mat<T>(ar_, R, hl[l + 1].perm, inv[l]);
         L.nnz_p = H.P.nnz();
         L.nnz_r = R.nnz();
         for (size_t c = 0; c + 1 < L.coff.size(); ++c) {
@@ -234,7 +281,7 @@ class Precond final : public PrecondBase {
   void sweep(int l, int cur, bool zero, hipStream_t s) {
     Level& L = lv_[l];
     T* S[2] = {L.s0, L.s1};
-    const SellView<T> A = L.A.view();
+    const MatView<T> A = L.A.view();
     for (size_t c = 0; c + 1 < L.coff.size(); ++c) {
       const bool timed = timer && l == 0;
       if (timed) timer->begin(CPR_KSTAT_SMOOTH_L0, s);

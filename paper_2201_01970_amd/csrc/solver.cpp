@@ -121,6 +121,7 @@ void cpr_handle::build_precond() {
     HIPCHK(hipMemcpy(h_vals.data(), d_vals_in, h_vals.size() * sizeof(double), hipMemcpyDeviceToHost));
     h_vals_valid = true;
   }
+  drop_graphs();
   pc.reset();
   hl.clear();
 
@@ -234,6 +235,42 @@ void cpr_handle::spmv(const double* x, double* y) {
   launch_bsr_spmv<double, double>(outer.view(), x, nullptr, y, stream);
 }
 
+void cpr_handle::drop_graphs() {
+  for (hipGraphExec_t& g : step_graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  step_graph.clear();
+}
+
+// One FGMRES step j: z_j = B v_j; w = A z_j (written into v_{j+1});
+// h_ij = (w, v_i) for i <= j (all against the same w: classical Gram-Schmidt);
+// w -= sum h_ij v_i; h_{j+1,j} = ||w||; Givens update; v_{j+1} = w / h_{j+1,j};
+// then |g_{j+1}| and h_{j+1,j} are copied to the host.
+void cpr_handle::step_body(int j, hipStream_t s) {
+  const int64_t N = 3 * static_cast<int64_t>(n_b);
+  const int64_t ld = N;
+  const int grid = krylov_grid(N);
+  const bool f32 = pc->fp32();
+  double* vj = V + j * ld;
+  double* w = V + (j + 1) * ld;
+  void* zj = f32 ? static_cast<void*>(static_cast<float*>(Z) + j * ld)
+                 : static_cast<void*>(static_cast<double*>(Z) + j * ld);
+  pc->apply(vj, zj, s);
+  if (prof.on()) prof.begin(CPR_KSTAT_SPMV, s);
+  if (f32)
+    launch_bsr_spmv<double, float>(outer.view(), static_cast<const float*>(zj), nullptr, w, s);
+  else
+    launch_bsr_spmv<double, double>(outer.view(), static_cast<const double*>(zj), nullptr, w, s);
+  if (prof.on())
+    prof.end(CPR_KSTAT_SPMV, s, 9.0 * nnz_b * 8 + 4.0 * nnz_b + 4.0 * (n_b + 1) + 3.0 * n_b * ((f32 ? 4 : 8) + 8));
+  launch_multidot(N, w, V, ld, 0, j + 1, partial, s);
+  double* Hj = H + static_cast<int64_t>(j) * (m + 1);
+  launch_reduce_partials(partial, grid, j + 1, Hj, s);
+  launch_axpy_norm(N, w, V, ld, 0, j + 1, Hj, norm_partial, s);
+  launch_givens(m, j, norm_partial, grid, H, cs, sn, g, hnorm, report_d, s);
+  launch_scale_div(N, w, hnorm, w, s);
+  HIPCHK(hipMemcpyAsync(report_h, report_d, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+}
+
 // ------------------------------------------------------------------ SOLVE
 // Flexible GMRES(m), classical Gram-Schmidt, Givens rotations.  Convergence:
 // ||r|| / ||r_0|| < tol checked on the Givens estimate after every step and
@@ -264,9 +301,6 @@ cpr_status cpr_handle::solve(const double* b, double* x, double tol, cpr_solve_i
   const int grid = krylov_grid(N);
   const bool f32 = pc->fp32();
   const int64_t ld = N;
-  auto Zj = [&](int j) -> void* {
-    return f32 ? static_cast<void*>(static_cast<float*>(Z) + j * ld) : static_cast<void*>(static_cast<double*>(Z) + j * ld);
-  };
   auto sync_report = [&]() {
     HIPCHK(hipMemcpyAsync(report_h, report_d, 4 * sizeof(double), hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
@@ -305,23 +339,25 @@ cpr_status cpr_handle::solve(const double* b, double* x, double tol, cpr_solve_i
       int k = 0;
       bool bad = false;
       for (int j = 0; j < m; ++j) {
-        double* vj = V + j * ld;
-        double* w = V + (j + 1) * ld;
-        pc->apply(vj, Zj(j), stream);
-        if (prof.on()) prof.begin(CPR_KSTAT_SPMV, stream);
-        if (f32)
-          launch_bsr_spmv<double, float>(outer.view(), static_cast<const float*>(Zj(j)), nullptr, w, stream);
-        else
-          launch_bsr_spmv<double, double>(outer.view(), static_cast<const double*>(Zj(j)), nullptr, w, stream);
-        if (prof.on())
-          prof.end(CPR_KSTAT_SPMV, stream,
-                   9.0 * nnz_b * 8 + 4.0 * nnz_b + 4.0 * (n_b + 1) + 3.0 * n_b * ((f32 ? 4 : 8) + 8));
-        launch_multidot(N, w, V, ld, 0, j + 1, partial, stream);
-        double* Hj = H + static_cast<int64_t>(j) * (m + 1);
-        launch_reduce_partials(partial, grid, j + 1, Hj, stream);
-        launch_axpy_norm(N, w, V, ld, 0, j + 1, Hj, norm_partial, stream);
-        launch_givens(m, j, norm_partial, grid, H, cs, sn, g, hnorm, report_d, stream);
-        sync_report();
+        if (prm.use_graphs && !prof.on()) {
+          if (step_graph.empty()) step_graph.assign(m, nullptr);
+          if (!step_graph[j]) {
+            if (!cap_stream) HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+            hipGraph_t graph = nullptr;
+            HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+            step_body(j, cap_stream);
+            HIPCHK(hipStreamEndCapture(cap_stream, &graph));
+            hipGraphExec_t exec = nullptr;
+            const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIPCHK(e);
+            step_graph[j] = exec;
+          }
+          HIPCHK(hipGraphLaunch(step_graph[j], stream));
+        } else {
+          step_body(j, stream);
+        }
+        HIPCHK(hipStreamSynchronize(stream));
         ++its;
         k = j + 1;
         est = report_h[0] / beta0;
@@ -331,7 +367,6 @@ cpr_status cpr_handle::solve(const double* b, double* x, double tol, cpr_solve_i
           break;
         }
         if (hn == 0.0) break;  // happy breakdown
-        launch_scale_div(N, w, hnorm, w, stream);
         if (est < tol) break;
       }
       if (bad) {

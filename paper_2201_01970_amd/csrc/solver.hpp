@@ -170,6 +170,12 @@ struct cpr_handle {
   cpr::Profiler prof;
   std::string last_error;
 
+  // one captured graph per FGMRES step index j (dropped whenever SETUP reruns)
+  std::vector<hipGraphExec_t> step_graph;
+  hipStream_t cap_stream = nullptr;
+  void drop_graphs();
+  void step_body(int j, hipStream_t s);
+
   void build_precond();
   cpr_status solve(const double* b, double* x, double tol, cpr_solve_info* info);
   void spmv(const double* x, double* y);

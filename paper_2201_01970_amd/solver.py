@@ -28,12 +28,14 @@ class Params:
     reuse_mode: int = 2
     mu: int = 20
     reuse_factor: float = 1.3
+    use_graphs: bool = True
 
     def to_c(self) -> A.cpr_params:
         p = A.cpr_params()
         for name, _ in A.cpr_params._fields_:
             setattr(p, name, getattr(self, name))
         p.precond_fp32 = int(bool(self.precond_fp32))
+        p.use_graphs = int(bool(self.use_graphs))
         return p
 
 

@@ -143,3 +143,26 @@ def test_fp32_preconditioner_solve(setup_pair):
     assert rel < 1e-6
     assert abs(info["iterations"] - info64["iterations"]) <= max(1, 0.1 * info64["iterations"])
     S32.close()
+
+
+def test_graph_replay_matches_eager(setup_pair):
+    """Each FGMRES step replayed as a captured graph gives the eager result bit for bit,
+    on every replay, with eager work and synchronisations in between."""
+    from paper_2201_01970_amd import Params, Solver
+
+    name, case, A, B, b, S = setup_pair
+    for fp32 in (False, True):
+        Se = Solver(_dev(case.row_ptr), _dev(case.col), _dev(case.vals.reshape(-1)),
+                    Params(precond_fp32=fp32, use_graphs=False))
+        Sg = Solver(_dev(case.row_ptr), _dev(case.col), _dev(case.vals.reshape(-1)),
+                    Params(precond_fp32=fp32, use_graphs=True))
+        xe, ie = Se.solve(_dev(b), tol=1e-6)
+        xe = xe.cpu().numpy()
+        for rep in range(3):
+            xg, ig = Sg.solve(_dev(b), tol=1e-6)
+            assert ig["iterations"] == ie["iterations"]
+            assert np.array_equal(xg.cpu().numpy(), xe), (fp32, rep)
+            Se.spmv(_dev(xe))  # eager work between replays
+            torch.cuda.synchronize()
+        Se.close()
+        Sg.close()
