@@ -79,6 +79,12 @@ typedef struct {
   int32_t mu;             /* threshold of reuse_mode 1 [20] */
   double reuse_factor;    /* factor of reuse_mode 2 [1.3] */
   int32_t use_graphs;     /* 1: replay each FGMRES step as one captured HIP graph [1] */
+  int32_t tail_nnz;       /* AMG levels from the first one whose own and every coarser
+                             level's matrix holds at most this many entries are run as
+                             one single-workgroup V-cycle kernel; 0 = never [30000] */
+  int32_t row_layout;     /* storage of AMG level matrices: 0 = chosen per matrix from its
+                             size and row lengths; 1 = one lane per row (SELL-64) everywhere;
+                             16/32/64 = CSR read by lane groups of that size everywhere [0] */
 } cpr_params;
 
 typedef struct {

@@ -60,6 +60,8 @@ class cpr_params(C.Structure):
         ("mu", C.c_int32),
         ("reuse_factor", C.c_double),
         ("use_graphs", C.c_int32),
+        ("tail_nnz", C.c_int32),
+        ("row_layout", C.c_int32),
     ]
 
 

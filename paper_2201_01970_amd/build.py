@@ -24,6 +24,7 @@ SOURCES = [
     "kernels_fine.hip",
     "kernels_amg.hip",
     "kernels_krylov.hip",
+    "kernels_tail.hip",
 ]
 
 ARCH = os.environ.get("CPR_OFFLOAD_ARCH", "gfx950")

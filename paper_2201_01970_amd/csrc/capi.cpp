@@ -137,6 +137,8 @@ void cpr_params_default(cpr_params* p) {
   p->mu = 20;
   p->reuse_factor = 1.3;
   p->use_graphs = 1;
+  p->tail_nnz = 30000;
+  p->row_layout = 0;
 }
 
 cpr_status cpr_setup(const cpr_bsr* A, const cpr_params* p, void* hip_stream, cpr_handle** out) {
@@ -150,7 +152,9 @@ cpr_status cpr_setup(const cpr_bsr* A, const cpr_params* p, void* hip_stream, cp
     if (p) prm = *p;
     if (prm.restart < 1 || prm.restart > 256 || prm.max_restarts < 1 || prm.coarse_max < 1 || prm.max_levels < 1 ||
         prm.pre_sweeps < 0 || prm.post_sweeps < 0 || !(prm.theta_rs >= 0.0) || !(prm.theta_color >= 0.0) ||
-        prm.reuse_mode < 0 || prm.reuse_mode > 2)
+        prm.reuse_mode < 0 || prm.reuse_mode > 2 || prm.tail_nnz < 0 ||
+        !(prm.row_layout == 0 || prm.row_layout == 1 || prm.row_layout == 16 || prm.row_layout == 32 ||
+          prm.row_layout == 64))
       throw Error(CPR_ERR_INVALID_ARG, "invalid parameters");
     h = new cpr_handle();
     h->prm = prm;

@@ -102,6 +102,29 @@ void launch_csr_spmv(const MatView<T>& A, const T* x, T* y, hipStream_t s);
 template <typename T>
 void launch_prolong_add(const MatView<T>& P, const T* e, T* x, T* snap, hipStream_t s);
 
+// Device-resident description of one level handled by the one-workgroup tail
+// V-cycle (all matrices CSR, rows in colour order; P maps the next level to
+// this one, R this level to the next).
+template <typename T>
+struct TailLevel {
+  int32_t n = 0, ncol = 0;
+  const int32_t* coff = nullptr;
+  const int32_t *a_rp = nullptr, *a_col = nullptr;
+  const T *a_val = nullptr, *diag = nullptr;
+  const int32_t *p_rp = nullptr, *p_col = nullptr;
+  const T* p_val = nullptr;
+  const int32_t *r_rp = nullptr, *r_col = nullptr;
+  const T* r_val = nullptr;
+  T *x = nullptr, *b = nullptr, *r = nullptr, *s0 = nullptr, *s1 = nullptr;
+};
+
+// V-cycle of the levels levels[0..nlev-1] (the last one the coarsest, solved
+// with the FP64 LU factors) in one workgroup; levels[0].b is the input and
+// levels[0].x the output.
+template <typename T>
+void launch_tail_vcycle(const TailLevel<T>* levels, int nlev, int pre, int post, int32_t n_coarse, const double* lu,
+                        const int32_t* piv, hipStream_t s);
+
 // Dense LU solve on one workgroup: x = A^{-1} b with FP64 factors.
 template <typename T>
 void launch_coarse_solve(int32_t n, const double* lu, const int32_t* piv, const T* b, T* x, hipStream_t s);

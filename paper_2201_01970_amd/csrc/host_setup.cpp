@@ -2,11 +2,71 @@
 #include "host_setup.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <queue>
+#include <thread>
 #include <utility>
 
 namespace cpr {
+
+int setup_threads() {
+  const unsigned hw = std::thread::hardware_concurrency();
+  return static_cast<int>(std::max(1u, std::min(hw, 16u)));
+}
+
+namespace {
+
+// Run f(chunk, thread) for chunk = 0..n_chunks-1 on up to setup_threads()
+// threads; `thread` indexes per-thread scratch.
+template <typename F>
+void parallel_chunks(int n_chunks, F&& f) {
+  const int nt = std::min(setup_threads(), n_chunks);
+  if (nt <= 1) {
+    for (int c = 0; c < n_chunks; ++c) f(c, 0);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&, t]() {
+      for (int c = next++; c < n_chunks; c = next++) f(c, t);
+    });
+  for (auto& th : pool) th.join();
+}
+
+int n_workers(int n_chunks) { return std::max(1, std::min(setup_threads(), n_chunks)); }
+
+// Rows [0, n) split into chunks; each chunk appends its rows' entries to its
+// own buffers, which are then concatenated in row order.  The result does not
+// depend on the thread count.
+struct RowChunks {
+  int32_t n_rows = 0, n_chunks = 0;
+  std::vector<std::vector<int32_t>> col;
+  std::vector<std::vector<double>> val;
+  std::vector<int32_t> row_len;
+  explicit RowChunks(int32_t n) : n_rows(n) {
+    n_chunks = static_cast<int32_t>(std::min<int64_t>(std::max<int64_t>(1, n / 2048), 256));
+    col.resize(n_chunks);
+    val.resize(n_chunks);
+    row_len.assign(n, 0);
+  }
+  int32_t begin(int c) const { return static_cast<int32_t>(static_cast<int64_t>(n_rows) * c / n_chunks); }
+  int32_t end(int c) const { return static_cast<int32_t>(static_cast<int64_t>(n_rows) * (c + 1) / n_chunks); }
+  void gather(HostCsr& out) {
+    out.ptr.assign(n_rows + 1, 0);
+    for (int32_t i = 0; i < n_rows; ++i) out.ptr[i + 1] = out.ptr[i] + row_len[i];
+    out.col.resize(out.ptr[n_rows]);
+    out.val.resize(out.ptr[n_rows]);
+    parallel_chunks(n_chunks, [&](int c, int) {
+      const int32_t off = out.ptr[begin(c)];
+      std::copy(col[c].begin(), col[c].end(), out.col.begin() + off);
+      std::copy(val[c].begin(), val[c].end(), out.val.begin() + off);
+    });
+  }
+};
+
+}  // namespace
 
 Pattern pattern_from_mask(const HostCsr& A, const std::vector<uint8_t>& mask, uint8_t bit) {
   Pattern S;
@@ -62,6 +122,7 @@ int32_t vertices_grouping(const Pattern& S, std::vector<int32_t>& colour) {
   std::vector<int32_t> infl(n);
   for (int32_t i = 0; i < n; ++i) infl[i] = S.ptr[i + 1] - S.ptr[i];
   std::vector<int8_t> state(n, kOutside);
+  std::vector<int32_t> in_front(n, -1);  // round in which the vertex entered the frontier
   std::vector<int32_t> V(n);
   for (int32_t i = 0; i < n; ++i) V[i] = i;
   std::vector<int32_t> Wbar;
@@ -108,7 +169,11 @@ int32_t vertices_grouping(const Pattern& S, std::vector<int32_t>& colour) {
           int32_t k = S.col[p];
           for (int32_t q = S.ptr[k]; q < S.ptr[k + 1]; ++q) {
             int32_t j = S.col[q];
-            if (state[j] == kUndecided) heap_f.push({infl[j], j});
+            // keys are static, so one frontier entry per vertex and round suffices
+            if (state[j] == kUndecided && in_front[j] != c) {
+              in_front[j] = c;
+              heap_f.push({infl[j], j});
+            }
           }
         }
       } else {
@@ -247,60 +312,71 @@ bool rs_interpolation(const HostCsr& A, const std::vector<uint8_t>& mask, uint8_
   P = HostCsr();
   P.n_rows = n;
   P.n_cols = nc;
-  P.ptr.assign(n + 1, 0);
-  std::vector<int32_t> in_ci(n, -1);
-  std::vector<double> num(n, 0.0);
-  bool ok = true;
-  for (int32_t i = 0; i < n; ++i) {
-    const int32_t a0 = A.ptr[i], a1 = A.ptr[i + 1];
-    if (cf[i] == C) {
-      P.col.push_back(coarse[i]);
-      P.val.push_back(1.0);
-      P.ptr[i + 1] = static_cast<int32_t>(P.col.size());
-      continue;
+  RowChunks rc(n);
+  std::atomic<bool> ok{true};
+  // per-thread marks, indexed by fine row and stamped with the current row
+  const int nw = n_workers(rc.n_chunks);
+  std::vector<std::vector<int32_t>> in_ci_t(nw);
+  std::vector<std::vector<double>> num_t(nw);
+  parallel_chunks(rc.n_chunks, [&](int ch, int t) {
+    std::vector<int32_t>& pc = rc.col[ch];
+    std::vector<double>& pv = rc.val[ch];
+    if (in_ci_t[t].empty()) {
+      in_ci_t[t].assign(n, -1);
+      num_t[t].assign(n, 0.0);
     }
-    bool any_c = false;
-    for (int32_t p = a0; p < a1; ++p)
-      if ((mask[p] & bit) && cf[A.col[p]] == C) {
-        in_ci[A.col[p]] = i;
-        num[A.col[p]] = A.val[p];
-        any_c = true;
-      }
-    if (!any_c) {
-      P.ptr[i + 1] = static_cast<int32_t>(P.col.size());
-      continue;
-    }
-    double d = 0.0;
-    for (int32_t p = a0; p < a1; ++p)
-      if (A.col[p] == i) d = A.val[p];
-    for (int32_t p = a0; p < a1; ++p)
-      if (A.col[p] != i && !(mask[p] & bit)) d = d + A.val[p];
-    for (int32_t p = a0; p < a1; ++p) {
-      const int32_t m = A.col[p];
-      if (!(mask[p] & bit) || cf[m] != F) continue;
-      const double a_im = A.val[p];
-      double den = 0.0;
-      for (int32_t q = A.ptr[m]; q < A.ptr[m + 1]; ++q)
-        if (in_ci[A.col[q]] == i) den = den + A.val[q];
-      if (den == 0.0) {
-        d = d + a_im;
+    std::vector<int32_t>& in_ci = in_ci_t[t];
+    std::vector<double>& num = num_t[t];
+    for (int32_t i = rc.begin(ch); i < rc.end(ch); ++i) {
+      const size_t before = pc.size();
+      const int32_t a0 = A.ptr[i], a1 = A.ptr[i + 1];
+      if (cf[i] == C) {
+        pc.push_back(coarse[i]);
+        pv.push_back(1.0);
+        rc.row_len[i] = 1;
         continue;
       }
-      for (int32_t q = A.ptr[m]; q < A.ptr[m + 1]; ++q) {
-        const int32_t k = A.col[q];
-        if (in_ci[k] == i) num[k] = num[k] + (a_im * A.val[q]) / den;
+      bool any_c = false;
+      for (int32_t p = a0; p < a1; ++p)
+        if ((mask[p] & bit) && cf[A.col[p]] == C) {
+          in_ci[A.col[p]] = i;
+          num[A.col[p]] = A.val[p];
+          any_c = true;
+        }
+      if (!any_c) continue;
+      double d = 0.0;
+      for (int32_t p = a0; p < a1; ++p)
+        if (A.col[p] == i) d = A.val[p];
+      for (int32_t p = a0; p < a1; ++p)
+        if (A.col[p] != i && !(mask[p] & bit)) d = d + A.val[p];
+      for (int32_t p = a0; p < a1; ++p) {
+        const int32_t m = A.col[p];
+        if (!(mask[p] & bit) || cf[m] != F) continue;
+        const double a_im = A.val[p];
+        double den = 0.0;
+        for (int32_t q = A.ptr[m]; q < A.ptr[m + 1]; ++q)
+          if (in_ci[A.col[q]] == i) den = den + A.val[q];
+        if (den == 0.0) {
+          d = d + a_im;
+          continue;
+        }
+        for (int32_t q = A.ptr[m]; q < A.ptr[m + 1]; ++q) {
+          const int32_t k = A.col[q];
+          if (in_ci[k] == i) num[k] = num[k] + (a_im * A.val[q]) / den;
+        }
       }
-    }
-    if (d == 0.0) ok = false;
-    for (int32_t p = a0; p < a1; ++p) {
-      const int32_t j = A.col[p];
-      if ((mask[p] & bit) && cf[j] == C) {
-        P.col.push_back(coarse[j]);
-        P.val.push_back(-num[j] / d);
+      if (d == 0.0) ok = false;
+      for (int32_t p = a0; p < a1; ++p) {
+        const int32_t j = A.col[p];
+        if ((mask[p] & bit) && cf[j] == C) {
+          pc.push_back(coarse[j]);
+          pv.push_back(-num[j] / d);
+        }
       }
+      rc.row_len[i] = static_cast<int32_t>(pc.size() - before);
     }
-    P.ptr[i + 1] = static_cast<int32_t>(P.col.size());
-  }
+  });
+  rc.gather(P);
   return ok;
 }
 
@@ -327,33 +403,45 @@ HostCsr spgemm_ordered(const HostCsr& A, const HostCsr& B) {
   HostCsr Cm;
   Cm.n_rows = A.n_rows;
   Cm.n_cols = B.n_cols;
-  Cm.ptr.assign(A.n_rows + 1, 0);
-  std::vector<double> acc(B.n_cols, 0.0);
-  std::vector<int32_t> seen(B.n_cols, -1);
-  std::vector<int32_t> touched;
-  for (int32_t i = 0; i < A.n_rows; ++i) {
-    touched.clear();
-    for (int32_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
-      const int32_t k = A.col[p];
-      const double a = A.val[p];
-      for (int32_t q = B.ptr[k]; q < B.ptr[k + 1]; ++q) {
-        const int32_t j = B.col[q];
-        if (seen[j] != i) {
-          seen[j] = i;
-          acc[j] = 0.0;
-          touched.push_back(j);
+  RowChunks rc(A.n_rows);
+  const int nw = n_workers(rc.n_chunks);
+  std::vector<std::vector<double>> acc_t(nw);
+  std::vector<std::vector<int32_t>> seen_t(nw), touched_t(nw);
+  parallel_chunks(rc.n_chunks, [&](int ch, int t) {
+    std::vector<int32_t>& cc = rc.col[ch];
+    std::vector<double>& cv = rc.val[ch];
+    if (seen_t[t].empty()) {
+      acc_t[t].assign(B.n_cols, 0.0);
+      seen_t[t].assign(B.n_cols, -1);
+    }
+    std::vector<double>& acc = acc_t[t];
+    std::vector<int32_t>& seen = seen_t[t];
+    std::vector<int32_t>& touched = touched_t[t];
+    for (int32_t i = rc.begin(ch); i < rc.end(ch); ++i) {
+      touched.clear();
+      for (int32_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+        const int32_t k = A.col[p];
+        const double a = A.val[p];
+        for (int32_t q = B.ptr[k]; q < B.ptr[k + 1]; ++q) {
+          const int32_t j = B.col[q];
+          if (seen[j] != i) {
+            seen[j] = i;
+            acc[j] = 0.0;
+            touched.push_back(j);
+          }
+          const double prod = a * B.val[q];
+          acc[j] = acc[j] + prod;
         }
-        const double prod = a * B.val[q];
-        acc[j] = acc[j] + prod;
       }
+      std::sort(touched.begin(), touched.end());
+      for (int32_t j : touched) {
+        cc.push_back(j);
+        cv.push_back(acc[j]);
+      }
+      rc.row_len[i] = static_cast<int32_t>(touched.size());
     }
-    std::sort(touched.begin(), touched.end());
-    for (int32_t j : touched) {
-      Cm.col.push_back(j);
-      Cm.val.push_back(acc[j]);
-    }
-    Cm.ptr[i + 1] = static_cast<int32_t>(Cm.col.size());
-  }
+  });
+  rc.gather(Cm);
   return Cm;
 }
 

@@ -5,7 +5,7 @@
 //  * SELL-64, one lane per row (short rows: the finest level, P, R).  Slots
 //    are fetched kUnroll at a time so the gathers of a row overlap.
 //  * CSR with a group of 16, 32 or 64 lanes per row (long rows of the
-//    Galerkin levels).  Each lane fetches one stored entry of a chunk (two
+//    Galerkin levels).  Each lane fetches one stored entry of a chunk (four
 //    chunks in flight) and forms its product; the group then adds the
 //    products in stored order, broadcast one lane at a time (through the
 //    scalar unit when the group is the whole wavefront).
@@ -18,7 +18,7 @@
 namespace cpr {
 
 constexpr int kUnroll = 8;
-constexpr int kChunks = 2;  // chunks of a long row whose loads are issued together
+constexpr int kChunks = 4;  // chunks of a row whose loads are issued together
 
 // ------------------------------------------------------------------ helpers
 // Row q of a SELL matrix: call f(col, val) for each stored entry in order,

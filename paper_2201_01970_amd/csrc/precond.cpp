@@ -48,14 +48,22 @@ SellHost build_sell(const HostCsr& A, const std::vector<int32_t>& order, const s
   return S;
 }
 
-// A level matrix on the device in the form its row lengths call for: SELL-64
-// (one lane per row) when rows are short, CSR read by lane groups of 16, 32 or
-// 64 when the average row holds more than kLongRow entries.
-constexpr double kLongRow = 12.0;
+// A level matrix on the device in the form its size and row lengths call for.
+// One lane per row (SELL-64) costs two ALU operations per entry but needs many
+// rows in flight to hide the gather latency of its sequential row walk; a lane
+// group per row (CSR) issues a whole row's loads at once, so small levels finish
+// in one memory round trip, at the price of the in-order broadcast sum.  SELL is
+// chosen when the matrix has at least kSellRows rows of at most kSellAvg entries
+// on average, lane groups otherwise (16 lanes up to 64 entries per row at the
+// maximum, 32 up to 128, else 64: one round of kChunks chunks per row).
+constexpr int32_t kSellRows = 100000;
+constexpr double kSellAvg = 40.0;
 
-int32_t group_for(double avg) {
-  if (avg <= 24.0) return 16;
-  if (avg <= 48.0) return 32;
+int32_t layout_for(int32_t policy, int32_t n, double avg, int32_t maxlen) {
+  if (policy != 0) return policy;
+  if (n >= kSellRows && avg <= kSellAvg) return 1;
+  if (maxlen <= 64) return 16;
+  if (maxlen <= 128) return 32;
   return 64;
 }
 
@@ -72,12 +80,16 @@ struct DevMat {
 
 template <typename T>
 DevMat<T> upload_mat(Arena& ar, const HostCsr& A, const std::vector<int32_t>& order,
-                     const std::vector<int32_t>& colmap) {
+                     const std::vector<int32_t>& colmap, int32_t policy, bool force_csr = false) {
   DevMat<T> D;
   const int32_t n = static_cast<int32_t>(order.size());
   D.n_rows = n;
   const double avg = n > 0 ? static_cast<double>(A.nnz()) / n : 0.0;
-  if (avg <= kLongRow) {
+  int32_t maxlen = 0;
+  for (int32_t i = 0; i < A.n_rows; ++i) maxlen = std::max(maxlen, A.ptr[i + 1] - A.ptr[i]);
+  int32_t layout = layout_for(policy, n, avg, maxlen);
+  if (force_csr) layout = 16;
+  if (layout == 1) {
     const SellHost S = build_sell(A, order, colmap);
     D.group = 1;
     D.stored = static_cast<int64_t>(S.col.size());
@@ -99,7 +111,7 @@ DevMat<T> upload_mat(Arena& ar, const HostCsr& A, const std::vector<int32_t>& or
     }
     rp[p + 1] = static_cast<int32_t>(col.size());
   }
-  D.group = group_for(avg);
+  D.group = layout;
   D.stored = static_cast<int64_t>(col.size());
   D.ptr = ar.upload(rp);
   D.col = ar.upload(col);
@@ -126,6 +138,7 @@ class Precond final : public PrecondBase {
     DevMat<T> A, P, R;
     T *diag = nullptr, *x = nullptr, *b = nullptr, *r = nullptr, *s0 = nullptr, *s1 = nullptr;
     int32_t* perm = nullptr;
+    int32_t* coff_d = nullptr;
   };
 
   Precond(const cpr_params& prm, int32_t n_b, const std::vector<HostLevel>& hl, const std::vector<double>& lu,
@@ -138,9 +151,14 @@ class Precond final : public PrecondBase {
     const double sv = sizeof(T);
     std::vector<std::vector<int32_t>> inv(nl);
     for (int l = 0; l < nl; ++l) inv[l] = inverse_perm(hl[l].perm);
+    // first level of the one-workgroup tail: every level from it down is small
+    tail_ = nl - 1;
+    if (prm.tail_nnz > 0)
+      while (tail_ > 0 && hl[tail_ - 1].A.nnz() <= prm.tail_nnz) --tail_;
     for (int l = 0; l < nl; ++l) {
       Level& L = lv_[l];
       const HostLevel& H = hl[l];
+      const bool in_tail = l >= tail_;
       L.n = H.A.n_rows;
       L.nnz = H.A.nnz();
       L.coff = H.coff;
@@ -148,7 +166,7 @@ class Precond final : public PrecondBase {
       L.x = ar_.alloc<T>(L.n);
       L.b = ar_.alloc<T>(L.n);
       if (l + 1 < nl) {
-        L.A = upload_mat<T>(ar_, H.A, H.perm, inv[l]);
+        L.A = upload_mat<T>(ar_, H.A, H.perm, inv[l], prm.row_layout, in_tail);
         std::vector<T> dg(L.n);
         for (int32_t p = 0; p < L.n; ++p) {
           const int32_t i = H.perm[p];
@@ -161,9 +179,9 @@ class Precond final : public PrecondBase {
         L.r = ar_.alloc<T>(L.n);
         L.s0 = ar_.alloc<T>(L.n);
         L.s1 = ar_.alloc<T>(L.n);
-        L.P = upload_mat<T>(ar_, H.P, H.perm, inv[l + 1]);
+        L.P = upload_mat<T>(ar_, H.P, H.perm, inv[l + 1], prm.row_layout, in_tail);
         const HostCsr R = transpose(H.P);
-        L.R = upload_mat<T>(ar_, R, hl[l + 1].perm, inv[l]);
+        L.R = upload_mat<T>(ar_, R, hl[l + 1].perm, inv[l], prm.row_layout, in_tail);
         L.nnz_p = H.P.nnz();
         L.nnz_r = R.nnz();
         for (size_t c = 0; c + 1 < L.coff.size(); ++c) {
@@ -180,6 +198,35 @@ class Precond final : public PrecondBase {
     nL_ = lv_.back().n;
     lu_ = ar_.upload(lu);
     piv_ = ar_.upload(piv);
+    // device descriptors of the tail levels
+    std::vector<TailLevel<T>> td(nl - tail_);
+    for (int l = tail_; l < nl; ++l) {
+      Level& L = lv_[l];
+      TailLevel<T>& d = td[l - tail_];
+      d.n = L.n;
+      d.x = L.x;
+      d.b = L.b;
+      if (l + 1 < nl) {
+        L.coff_d = ar_.upload(L.coff);
+        d.ncol = static_cast<int32_t>(L.coff.size()) - 1;
+        d.coff = L.coff_d;
+        d.a_rp = L.A.ptr;
+        d.a_col = L.A.col;
+        d.a_val = L.A.val;
+        d.diag = L.diag;
+        d.p_rp = L.P.ptr;
+        d.p_col = L.P.col;
+        d.p_val = L.P.val;
+        d.r_rp = L.R.ptr;
+        d.r_col = L.R.col;
+        d.r_val = L.R.val;
+        d.r = L.r;
+        d.s0 = L.s0;
+        d.s1 = L.s1;
+      }
+    }
+    tail_dev_ = ar_.alloc<TailLevel<T>>(static_cast<int64_t>(td.size()));
+    HIPCHK(hipMemcpy(tail_dev_, td.data(), td.size() * sizeof(TailLevel<T>), hipMemcpyHostToDevice));
 
     // ---- fine level for stage 2: cells in block-colour order
     bcoff_ = bcoff;
@@ -293,8 +340,8 @@ class Precond final : public PrecondBase {
   void vcycle(int l, hipStream_t s) {
     Level& L = lv_[l];
     const int nl = static_cast<int>(lv_.size());
-    if (l == nl - 1) {
-      launch_coarse_solve<T>(L.n, lu_, piv_, L.b, L.x, s);
+    if (l == tail_) {
+      launch_tail_vcycle<T>(tail_dev_, nl - tail_, pre_, post_, nL_, lu_, piv_, s);
       return;
     }
     const double sv = sizeof(T);
@@ -325,6 +372,8 @@ class Precond final : public PrecondBase {
 
   Arena ar_;
   std::vector<Level> lv_;
+  int tail_ = 0;
+  TailLevel<T>* tail_dev_ = nullptr;
   int pre_, post_;
   int32_t n_b_;
   int32_t nL_ = 0;

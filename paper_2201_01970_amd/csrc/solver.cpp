@@ -125,6 +125,34 @@ void cpr_handle::build_precond() {
   pc.reset();
   hl.clear();
 
+  // every diagonal block must admit an LU with partial pivoting whose pivots
+  // exceed 1e-300 times the block's largest entry (same test as the device
+  // inversion, checked first so that no other SETUP step sees a singular block)
+  for (int32_t i = 0; i < n_b; ++i) {
+    int32_t d = -1;
+    for (int32_t k = h_row_ptr[i]; k < h_row_ptr[i + 1]; ++k)
+      if (h_col[k] == i) d = k;
+    double a[3][3], amax = 0.0;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        a[r][c] = h_vals[static_cast<size_t>(d) * 9 + 3 * r + c];
+        amax = std::max(amax, std::fabs(a[r][c]));
+      }
+    bool bad = !(amax > 0.0);
+    for (int k = 0; k < 3 && !bad; ++k) {
+      int p = k;
+      for (int r = k + 1; r < 3; ++r)
+        if (std::fabs(a[r][k]) > std::fabs(a[p][k])) p = r;
+      if (!(std::fabs(a[p][k]) > 1e-300 * amax)) bad = true;
+      for (int c = 0; c < 3; ++c) std::swap(a[k][c], a[p][c]);
+      for (int r = k + 1; r < 3 && !bad; ++r) {
+        const double l = a[r][k] / a[k][k];
+        for (int c = k + 1; c < 3; ++c) a[r][c] = a[r][c] - l * a[k][c];
+      }
+    }
+    if (bad) throw Error(CPR_ERR_SINGULAR_BLOCK, "diagonal block of cell " + std::to_string(i) + " is singular");
+  }
+
   HostCsr A;
   A.n_rows = A.n_cols = n_b;
   A.ptr = h_row_ptr;

@@ -29,6 +29,8 @@ class Params:
     mu: int = 20
     reuse_factor: float = 1.3
     use_graphs: bool = True
+    tail_nnz: int = 30000
+    row_layout: int = 0
 
     def to_c(self) -> A.cpr_params:
         p = A.cpr_params()

@@ -1,0 +1,121 @@
+"""Adaptive SETUP (Algorithm "ASCPR") on a Newton sequence, against the oracle,
+and the error paths of the C ABI.
+
+The sequence is the drifting-Jacobian generator (fixed pattern, +-5% value
+drift per step) on a 16x14x8 grid.  For each rule the GPU's rebuild
+decisions and iteration counts must equal the oracle's step by step (the
+decisions are a pure function of the iteration history, so they must agree
+exactly), and every step must reach the true relative residual.
+"""
+import numpy as np
+import pytest
+
+from oracle import ascpr, cpr
+from workloads import blackoil as bo
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+@pytest.fixture(scope="module")
+def sequence():
+    steps = list(bo.newton_sequence(n_steps=6, shape=(16, 14, 8)))
+    return [(c, b) for _, c, b in steps]
+
+
+RULES = [
+    dict(mode="factor", factor=1.3, reuse_mode=2, mu=0),
+    dict(mode="mu", factor=1.3, reuse_mode=1, mu=0),
+    dict(mode="mu", factor=1.3, reuse_mode=1, mu=10 ** 6),
+    dict(mode="mu", factor=1.3, reuse_mode=1, mu=6),
+]
+
+
+@pytest.mark.parametrize("rule", RULES, ids=lambda r: f"{r['mode']}-{r['mu']}")
+@pytest.mark.parametrize("fp32", [False, True])
+def test_sequence_matches_oracle(sequence, rule, fp32):
+    from paper_2201_01970_amd import Params, Solver
+
+    dt = np.float32 if fp32 else np.float64
+    reps = ascpr.solve_sequence([(cpr.Bsr.from_case(c), b) for c, b in sequence], mode=rule["mode"],
+                                mu=rule["mu"], factor=rule["factor"], dtype=dt)
+    c0 = sequence[0][0]
+    S = Solver(_dev(c0.row_ptr), _dev(c0.col), _dev(c0.vals.reshape(-1)),
+               Params(precond_fp32=fp32, reuse_mode=rule["reuse_mode"], mu=rule["mu"],
+                      reuse_factor=rule["factor"]))
+    for k, ((case, b), rep) in enumerate(zip(sequence, reps)):
+        if k > 0:
+            S.update_values(_dev(case.vals.reshape(-1)))
+        x, info = S.solve(_dev(b), tol=1e-6)
+        rel = np.linalg.norm(cpr.bsr_residual(cpr.Bsr.from_case(case), x.cpu().numpy(), b)) / np.linalg.norm(b)
+        print(f"[{rule['mode']}-{rule['mu']} fp32={fp32}] step {k}: gpu its={info['iterations']} "
+              f"rebuilt={info['rebuilt']} | oracle its={rep.iterations} rebuilt={rep.rebuilt} relres={rel:.2e}")
+        assert rel < 1e-6
+        if k > 0:
+            assert bool(info["rebuilt"]) == rep.rebuilt
+        if not fp32:
+            assert info["iterations"] == rep.iterations
+        else:
+            assert abs(info["iterations"] - rep.iterations) <= max(1, 0.1 * rep.iterations)
+    S.close()
+
+
+def test_error_paths(sequence):
+    from paper_2201_01970_amd import CprError, Params, Solver
+    from paper_2201_01970_amd import _capi as capi
+
+    case, b = sequence[0]
+    S = Solver(_dev(case.row_ptr), _dev(case.col), _dev(case.vals.reshape(-1)), Params())
+    # different size
+    small = bo.case_small(shape=(5, 4, 3))
+    with pytest.raises(CprError) as e:
+        S.update_values(_dev(small.vals.reshape(-1)), _dev(small.row_ptr), _dev(small.col))
+    assert e.value.status == capi.CPR_ERR_SIZE_MISMATCH
+    # same sizes, different pattern (two column indices of row 0 swapped out)
+    col = case.col.copy()
+    r0 = slice(case.row_ptr[1], case.row_ptr[2])
+    col[r0] = np.sort((col[r0] + 1) % case.n_b)
+    with pytest.raises(CprError) as e:
+        S.update_values(_dev(case.vals.reshape(-1)), _dev(case.row_ptr), _dev(col))
+    assert e.value.status in (capi.CPR_ERR_PATTERN_MISMATCH,)
+    # NaN in the right-hand side
+    bad = b.copy()
+    bad[7] = np.nan
+    with pytest.raises(CprError) as e:
+        S.solve(_dev(bad), tol=1e-6)
+    assert e.value.status == capi.CPR_ERR_NAN
+    # the handle still works afterwards
+    x, info = S.solve(_dev(b), tol=1e-6)
+    assert info["relres_true"] < 1e-6
+    # zero right-hand side: converged with zero iterations
+    x, info = S.solve(_dev(np.zeros_like(b)), tol=1e-6)
+    assert info["iterations"] == 0 and np.all(x.cpu().numpy() == 0)
+    S.close()
+
+
+def test_invalid_matrices_rejected():
+    from paper_2201_01970_amd import CprError, Params, Solver
+    from paper_2201_01970_amd import _capi as capi
+
+    case = bo.case_small(shape=(4, 4, 2))
+    # missing diagonal block in row 3
+    rp, col, vals = case.row_ptr.copy(), case.col.copy(), case.vals.copy()
+    keep = np.ones(case.nnz_b, dtype=bool)
+    d = rp[3] + int(np.nonzero(col[rp[3]:rp[4]] == 3)[0][0])
+    keep[d] = False
+    rp2 = rp.copy()
+    rp2[4:] -= 1
+    with pytest.raises(CprError) as e:
+        Solver(rp2, col[keep], vals[keep], Params())
+    assert e.value.status == capi.CPR_ERR_INVALID_ARG
+    # singular diagonal block
+    vals2 = vals.copy()
+    d0 = int(np.nonzero(col[rp[0]:rp[1]] == 0)[0][0])
+    vals2[d0] = 0.0
+    with pytest.raises(CprError) as e:
+        Solver(rp, col, vals2, Params())
+    assert e.value.status == capi.CPR_ERR_SINGULAR_BLOCK

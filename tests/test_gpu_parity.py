@@ -47,6 +47,12 @@ def setup_pair(request):
     S.close()
 
 
+def _solver(case, **kw):
+    from paper_2201_01970_amd import Params, Solver
+
+    return Solver(_dev(case.row_ptr), _dev(case.col), _dev(case.vals.reshape(-1)), Params(**kw))
+
+
 def test_spmv_bit_exact(setup_pair):
     name, case, A, B, b, S = setup_pair
     rng = np.random.default_rng(5)
@@ -104,23 +110,35 @@ def test_smoother_bit_exact(setup_pair):
         assert np.array_equal(got, want), l
 
 
-def test_vcycle_and_cpr_apply(setup_pair):
-    name, case, A, B, b, S = setup_pair
+@pytest.mark.parametrize("tail_nnz", [0, 30000, 10 ** 9])
+def test_vcycle_and_cpr_apply(setup_pair, tail_nnz):
+    """tail_nnz = 0: one kernel per colour on every level; 30000: the small
+    levels in the one-workgroup tail kernel; 1e9: the whole V-cycle in it.
+    The per-colour and tail paths are bit-identical to each other."""
+    name, case, A, B, b, S0 = setup_pair
+    S = _solver(case, tail_nnz=tail_nnz)
     rng = np.random.default_rng(7)
     r = rng.standard_normal(A.n_b)
     want = amg.vcycle(B.amg, r)
     got = S.vcycle(_dev(r)).cpu().numpy()
     assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+    S_ref = _solver(case, tail_nnz=0)
+    assert np.array_equal(got, S_ref.vcycle(_dev(r)).cpu().numpy())
     v = rng.standard_normal(case.ndof)
     want = B.apply(v)
     got = S.precond(_dev(v)).cpu().numpy()
     assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+    S.close()
+    S_ref.close()
 
 
-def test_fp64_solve_matches_oracle(setup_pair):
-    name, case, A, B, b, S = setup_pair
+@pytest.mark.parametrize("tail_nnz", [0, 30000])
+def test_fp64_solve_matches_oracle(setup_pair, tail_nnz):
+    name, case, A, B, b, S0 = setup_pair
+    S = _solver(case, tail_nnz=tail_nnz)
     res = fgmres.fgmres(lambda v: cpr.bsr_matvec(A, v), B.apply, b, tol=1e-6)
     x, info = S.solve(_dev(b), tol=1e-6)
+    S.close()
     x = x.cpu().numpy()
     print(f"[{name}] gpu its={info['iterations']} oracle its={res.iterations} relres={info['relres_true']:.3e}")
     assert info["iterations"] == res.iterations
