@@ -81,6 +81,25 @@ class cpr_solve_info(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class cpr_request(C.Structure):
+    _fields_ = [
+        ("case_id", C.c_int64),
+        ("A", cpr_bsr),
+        ("b", C.c_void_p),
+        ("x", C.c_void_p),
+        ("tol", C.c_double),
+    ]
+
+
+class cpr_server_stats(C.Structure):
+    _fields_ = [(name, C.c_int64) for name in (
+        "submitted", "completed", "rejected", "setups", "reuses", "evictions",
+        "resident_cases", "bytes_in_use", "bytes_peak", "budget_bytes")]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
 _P = C.c_void_p
 _I32 = C.c_int32
 _I64 = C.c_int64
@@ -112,6 +131,12 @@ SIGNATURES = {
     "cpr_profile_enable": (_I32, [_P, _I32]),
     "cpr_profile_read": (_I32, [_P, _I32, _P, _P, _P]),
     "cpr_copy_kernel": (_I32, [_P, _P, _I64, _P]),
+    "cpr_server_create": (_I32, [_I64, _I32, C.POINTER(cpr_params), C.POINTER(_P)]),
+    "cpr_server_submit": (_I32, [_P, C.POINTER(cpr_request), C.POINTER(_I64)]),
+    "cpr_server_wait": (_I32, [_P, _I64, C.POINTER(cpr_solve_info), C.POINTER(_D)]),
+    "cpr_server_stats_get": (_I32, [_P, C.POINTER(cpr_server_stats)]),
+    "cpr_server_destroy": (None, [_P]),
+    "cpr_server_last_error": (C.c_char_p, [_P]),
 }
 
 _lib = None

@@ -21,6 +21,7 @@ SOURCES = [
     "precond.cpp",
     "solver.cpp",
     "capi.cpp",
+    "serve.cpp",
     "kernels_fine.hip",
     "kernels_amg.hip",
     "kernels_krylov.hip",

@@ -33,9 +33,10 @@ cpr_status guarded(cpr_handle* h, F&& f) {
 
 void copy_in(void* dst, const void* src, size_t bytes, int32_t location) {
   if (bytes == 0) return;
-  if (location == CPR_MEM_DEVICE)
+  if (location == CPR_MEM_DEVICE) {
+    std::lock_guard<std::mutex> lk(device_api_mutex());
     HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
-  else
+  } else
     std::memcpy(dst, src, bytes);
 }
 
@@ -115,6 +116,7 @@ void alloc_krylov(cpr_handle* h) {
   h->norm_partial = h->fine.alloc<double>(grid);
   h->report_d = h->fine.alloc<double>(4);
   h->r = h->fine.alloc<double>(N);
+  std::lock_guard<std::mutex> lk(device_api_mutex());
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->report_h), 4 * sizeof(double), hipHostMallocDefault));
 }
 
@@ -233,10 +235,13 @@ void cpr_destroy(cpr_handle* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
   h->drop_graphs();
-  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   h->pc.reset();
   h->fine.release();
-  if (h->report_h) (void)hipHostFree(h->report_h);
+  {
+    std::lock_guard<std::mutex> lk(device_api_mutex());
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->report_h) (void)hipHostFree(h->report_h);
+  }
   delete h;
 }
 

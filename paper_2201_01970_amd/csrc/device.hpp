@@ -119,15 +119,11 @@ struct TailLevel {
 };
 
 // V-cycle of the levels levels[0..nlev-1] (the last one the coarsest, solved
-// with the FP64 LU factors) in one workgroup; levels[0].b is the input and
-// levels[0].x the output.
+// with the FP64 LU factors of P A = L U, rperm[i] = source row of row i of P b)
+// in one workgroup; levels[0].b is the input and levels[0].x the output.
 template <typename T>
 void launch_tail_vcycle(const TailLevel<T>* levels, int nlev, int pre, int post, int32_t n_coarse, const double* lu,
-                        const int32_t* piv, hipStream_t s);
-
-// Dense LU solve on one workgroup: x = A^{-1} b with FP64 factors.
-template <typename T>
-void launch_coarse_solve(int32_t n, const double* lu, const int32_t* piv, const T* b, T* x, hipStream_t s);
+                        const int32_t* rperm, hipStream_t s);
 
 // ---- setup kernel: strength masks (bit 1: RS strength, bit 2: eq. (strong-matrix))
 void launch_strength(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, double theta_rs,

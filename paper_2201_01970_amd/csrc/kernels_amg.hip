@@ -1,5 +1,5 @@
 // Pressure-AMG kernels: the PGS-SCM colour sweep (Algorithm "PGS-SCM"),
-// residual, restriction, prolongation and the dense coarsest solve.
+// residual, restriction and prolongation.
 //
 // Two storage forms, chosen per matrix at SETUP from its row lengths:
 //  * SELL-64, one lane per row (short rows: the finest level, P, R).  Slots
@@ -31,11 +31,12 @@ __device__ __forceinline__ void sell_row(int32_t q, const int32_t* __restrict__ 
   for (int32_t t = t0; t < t1; t += kUnroll) {
     int32_t c[kUnroll];
     T a[kUnroll];
+    // columns and values are requested together: padded slots hold value 0
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int64_t e = (int64_t)(t + u) * kWave + lane;
       c[u] = (t + u < t1) ? col[e] : kPadCol;
-      a[u] = (c[u] >= 0) ? val[e] : (T)0;
+      a[u] = (t + u < t1) ? val[e] : (T)0;
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) f(c[u], a[u]);
@@ -268,52 +269,5 @@ void launch_prolong_add(const MatView<T>& P, const T* e, T* x, T* snap, hipStrea
 CPR_INST_ROWS(double)
 CPR_INST_ROWS(float)
 #undef CPR_INST_ROWS
-
-// ------------------------------------------------------------------ coarsest solve
-// Dense LU solve in one workgroup (FP64): P A = L U with the row swaps applied
-// to b in factorisation order, unit-lower forward and upper back substitution.
-template <typename T>
-__global__ __launch_bounds__(1024) void k_coarse_solve(int32_t n, const double* __restrict__ lu,
-                                                       const int32_t* __restrict__ piv, const T* __restrict__ b,
-                                                       T* __restrict__ x) {
-  extern __shared__ double xs[];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < n; i += nt) xs[i] = (double)b[i];
-  __syncthreads();
-  if (tid == 0)
-    for (int k = 0; k < n; ++k) {
-      const int p = piv[k];
-      if (p != k) {
-        const double t = xs[k];
-        xs[k] = xs[p];
-        xs[p] = t;
-      }
-    }
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const double xk = xs[k];
-    for (int r = k + 1 + tid; r < n; r += nt) xs[r] = xs[r] - lu[(int64_t)r * n + k] * xk;
-    __syncthreads();
-  }
-  for (int k = n - 1; k >= 0; --k) {
-    if (tid == 0) xs[k] = xs[k] / lu[(int64_t)k * n + k];
-    __syncthreads();
-    const double xk = xs[k];
-    for (int r = tid; r < k; r += nt) xs[r] = xs[r] - lu[(int64_t)r * n + k] * xk;
-    __syncthreads();
-  }
-  for (int i = tid; i < n; i += nt) x[i] = (T)xs[i];
-}
-
-template <typename T>
-void launch_coarse_solve(int32_t n, const double* lu, const int32_t* piv, const T* b, T* x, hipStream_t s) {
-  if (n == 0) return;
-  const int threads = n >= 256 ? 1024 : 256;
-  hipLaunchKernelGGL((k_coarse_solve<T>), dim3(1), dim3(threads), n * sizeof(double), s, n, lu, piv, b, x);
-  CPR_LAUNCH_CHECK();
-}
-template void launch_coarse_solve<double>(int32_t, const double*, const int32_t*, const double*, double*,
-                                          hipStream_t);
-template void launch_coarse_solve<float>(int32_t, const double*, const int32_t*, const float*, float*, hipStream_t);
 
 }  // namespace cpr

@@ -12,7 +12,11 @@ namespace cpr {
 // ----------------------------------------------------------------- BSR SpMV
 // One lane per block row; the nine planes of a slot are read lane-contiguous.
 // y_r = sum over stored blocks (stored order) of a_r0*x0 + a_r1*x1 + a_r2*x2,
-// each product added separately (RESID: subtracted from b_r).
+// each product added separately (RESID: subtracted from b_r).  Slots are
+// fetched kSpmvUnroll at a time, columns and values together: a padded slot
+// has column -1 and zero values, so it reads x at cell 0 and adds zeros.
+constexpr int kSpmvUnroll = 2;
+
 template <typename TA, typename TX, bool RESID>
 __global__ __launch_bounds__(kBlock) void k_bsr_spmv(int32_t n, const int32_t* __restrict__ slice_ptr,
                                                      const int32_t* __restrict__ col,
@@ -32,23 +36,30 @@ __global__ __launch_bounds__(kBlock) void k_bsr_spmv(int32_t n, const int32_t* _
     y2 = 0.0;
   }
   const int32_t t0 = slice_ptr[slice], t1 = slice_ptr[slice + 1];
-  for (int32_t t = t0; t < t1; ++t) {
-    const int32_t c = col[(int64_t)t * kWave + lane];
-    if (c < 0) break;
-    const TA* vb = val + (int64_t)t * (9 * kWave) + lane;
-    const double x0 = (double)x[3 * (int64_t)c], x1 = (double)x[3 * (int64_t)c + 1],
-                 x2 = (double)x[3 * (int64_t)c + 2];
-    const double a00 = vb[0 * kWave], a01 = vb[1 * kWave], a02 = vb[2 * kWave];
-    const double a10 = vb[3 * kWave], a11 = vb[4 * kWave], a12 = vb[5 * kWave];
-    const double a20 = vb[6 * kWave], a21 = vb[7 * kWave], a22 = vb[8 * kWave];
-    if (RESID) {
-      y0 = y0 - a00 * x0; y0 = y0 - a01 * x1; y0 = y0 - a02 * x2;
-      y1 = y1 - a10 * x0; y1 = y1 - a11 * x1; y1 = y1 - a12 * x2;
-      y2 = y2 - a20 * x0; y2 = y2 - a21 * x1; y2 = y2 - a22 * x2;
-    } else {
-      y0 = y0 + a00 * x0; y0 = y0 + a01 * x1; y0 = y0 + a02 * x2;
-      y1 = y1 + a10 * x0; y1 = y1 + a11 * x1; y1 = y1 + a12 * x2;
-      y2 = y2 + a20 * x0; y2 = y2 + a21 * x1; y2 = y2 + a22 * x2;
+  for (int32_t t = t0; t < t1; t += kSpmvUnroll) {
+    int64_t c[kSpmvUnroll];
+    double a[kSpmvUnroll][9];
+#pragma unroll
+    for (int u = 0; u < kSpmvUnroll; ++u) {
+      const bool live = t + u < t1;
+      const int32_t cw = live ? col[(int64_t)(t + u) * kWave + lane] : kPadCol;
+      c[u] = cw < 0 ? 0 : cw;
+      const TA* vb = val + (int64_t)(t + u) * (9 * kWave) + lane;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) a[u][e] = live ? (double)vb[e * kWave] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kSpmvUnroll; ++u) {
+      const double x0 = (double)x[3 * c[u]], x1 = (double)x[3 * c[u] + 1], x2 = (double)x[3 * c[u] + 2];
+      if (RESID) {
+        y0 = y0 - a[u][0] * x0; y0 = y0 - a[u][1] * x1; y0 = y0 - a[u][2] * x2;
+        y1 = y1 - a[u][3] * x0; y1 = y1 - a[u][4] * x1; y1 = y1 - a[u][5] * x2;
+        y2 = y2 - a[u][6] * x0; y2 = y2 - a[u][7] * x1; y2 = y2 - a[u][8] * x2;
+      } else {
+        y0 = y0 + a[u][0] * x0; y0 = y0 + a[u][1] * x1; y0 = y0 + a[u][2] * x2;
+        y1 = y1 + a[u][3] * x0; y1 = y1 + a[u][4] * x1; y1 = y1 + a[u][5] * x2;
+        y2 = y2 + a[u][6] * x0; y2 = y2 + a[u][7] * x1; y2 = y2 + a[u][8] * x2;
+      }
     }
   }
   y[3 * (int64_t)row] = y0;
@@ -111,6 +122,8 @@ template void launch_scatter<double>(int32_t, const double*, const int32_t*, dou
 template void launch_scatter<float>(int32_t, const float*, const int32_t*, float*, hipStream_t);
 
 // ----------------------------------------------------------------- stage 2
+constexpr int kStage2Unroll = 4;
+
 // Rows of A are cells in block-colour order.  For the cells q in [lo, hi) of
 // one colour (cell i = cell[q]):
 //   t = v_i - sum_j A_ij zt_j,  zt_j = z_j (neighbour of an earlier colour,
@@ -131,25 +144,33 @@ __global__ __launch_bounds__(kBlock) void k_stage2(int32_t lo, int32_t hi, const
   const int64_t i = cell[q];
   T t0 = (T)v[3 * i], t1 = (T)v[3 * i + 1], t2 = (T)v[3 * i + 2];
   const int32_t s0 = slice_ptr[slice], s1 = slice_ptr[slice + 1];
-  for (int32_t t = s0; t < s1; ++t) {
-    const int32_t c = col[(int64_t)t * kWave + lane];
-    if (c == kPadCol) break;
-    const int64_t j = c & kColMask;
-    const T* vb = val + (int64_t)t * (9 * kWave) + lane;
-    if (c & kEarlierBit) {
-      const T z0 = z[3 * j], z1 = z[3 * j + 1], z2 = z[3 * j + 2];
-      const T a00 = vb[0 * kWave], a01 = vb[1 * kWave], a02 = vb[2 * kWave];
-      const T a10 = vb[3 * kWave], a11 = vb[4 * kWave], a12 = vb[5 * kWave];
-      const T a20 = vb[6 * kWave], a21 = vb[7 * kWave], a22 = vb[8 * kWave];
-      t0 = t0 - a00 * z0; t0 = t0 - a01 * z1; t0 = t0 - a02 * z2;
-      t1 = t1 - a10 * z0; t1 = t1 - a11 * z1; t1 = t1 - a12 * z2;
-      t2 = t2 - a20 * z0; t2 = t2 - a21 * z1; t2 = t2 - a22 * z2;
-    } else {
-      const T p = pe[j];
-      const T a00 = vb[0 * kWave], a10 = vb[3 * kWave], a20 = vb[6 * kWave];
-      t0 = t0 - a00 * p;
-      t1 = t1 - a10 * p;
-      t2 = t2 - a20 * p;
+  for (int32_t t = s0; t < s1; t += kStage2Unroll) {
+    // column words of a few slots first, then their value planes and vector
+    // entries together; padded slots (column -1) contribute nothing
+    int32_t cw[kStage2Unroll];
+#pragma unroll
+    for (int u = 0; u < kStage2Unroll; ++u) cw[u] = (t + u < s1) ? col[(int64_t)(t + u) * kWave + lane] : kPadCol;
+#pragma unroll
+    for (int u = 0; u < kStage2Unroll; ++u) {
+      const int32_t c = cw[u];
+      if (c == kPadCol) continue;
+      const int64_t j = c & kColMask;
+      const T* vb = val + (int64_t)(t + u) * (9 * kWave) + lane;
+      if (c & kEarlierBit) {
+        const T z0 = z[3 * j], z1 = z[3 * j + 1], z2 = z[3 * j + 2];
+        const T a00 = vb[0 * kWave], a01 = vb[1 * kWave], a02 = vb[2 * kWave];
+        const T a10 = vb[3 * kWave], a11 = vb[4 * kWave], a12 = vb[5 * kWave];
+        const T a20 = vb[6 * kWave], a21 = vb[7 * kWave], a22 = vb[8 * kWave];
+        t0 = t0 - a00 * z0; t0 = t0 - a01 * z1; t0 = t0 - a02 * z2;
+        t1 = t1 - a10 * z0; t1 = t1 - a11 * z1; t1 = t1 - a12 * z2;
+        t2 = t2 - a20 * z0; t2 = t2 - a21 * z1; t2 = t2 - a22 * z2;
+      } else {
+        const T p = pe[j];
+        const T a00 = vb[0 * kWave], a10 = vb[3 * kWave], a20 = vb[6 * kWave];
+        t0 = t0 - a00 * p;
+        t1 = t1 - a10 * p;
+        t2 = t2 - a20 * p;
+      }
     }
   }
   const T* d = dinv + q;

@@ -115,7 +115,7 @@ template <typename T>
 __global__ __launch_bounds__(kTailThreads) void k_tail_vcycle(const TailLevel<T>* __restrict__ levels, int nlev,
                                                                int pre, int post, int32_t n_coarse,
                                                                const double* __restrict__ lu,
-                                                               const int32_t* __restrict__ piv) {
+                                                               const int32_t* __restrict__ rperm) {
   extern __shared__ double xs[];
   // Snapshot bookkeeping: every sweep reads S[cur] and writes S[cur ^ 1], so
   // after the pre-sweeps S[pre & 1] equals x on every level.
@@ -134,36 +134,50 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_vcycle(const TailLevel<T>
     tail_rows<T, 1>(C.n, L.r_rp, L.r_col, L.r_val, nullptr, L.r, C.b, nullptr);
     __syncthreads();
   }
-  // coarsest: P A = L U in FP64, swaps in factorisation order
+  // coarsest: P A = L U in FP64.  rperm composes the row swaps of the
+  // factorisation, so (P b)_i = b[rperm[i]].
   {
     const TailLevel<T>& L = levels[nlev - 1];
     const int n = n_coarse;
-    for (int i = threadIdx.x; i < n; i += kTailThreads) xs[i] = (double)L.b[i];
-    __syncthreads();
-    if (threadIdx.x == 0)
-      for (int k = 0; k < n; ++k) {
-        const int p = piv[k];
-        if (p != k) {
-          const double t = xs[k];
-          xs[k] = xs[p];
-          xs[p] = t;
+    if (n <= kWave) {
+      // one wavefront, one row per lane, factors staged in LDS; the lanes stay
+      // in lockstep, so no barrier is needed between substitution steps
+      double* luS = xs + kWave;
+      for (int i = threadIdx.x; i < n * n; i += kTailThreads) luS[i] = lu[i];
+      __syncthreads();
+      if (threadIdx.x < kWave) {
+        const int r = threadIdx.x;
+        double xr = r < n ? (double)L.b[rperm[r]] : 0.0;
+        for (int k = 0; k < n; ++k) {
+          const double xk = __shfl(xr, k, kWave);
+          if (r > k && r < n) xr = xr - luS[r * n + k] * xk;
         }
+        for (int k = n - 1; k >= 0; --k) {
+          if (r == k) xr = xr / luS[k * n + k];
+          const double xk = __shfl(xr, k, kWave);
+          if (r < k) xr = xr - luS[r * n + k] * xk;
+        }
+        if (r < n) L.x[r] = (T)xr;
       }
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-      const double xk = xs[k];
-      for (int r = k + 1 + threadIdx.x; r < n; r += kTailThreads) xs[r] = xs[r] - lu[(int64_t)r * n + k] * xk;
+      __syncthreads();
+    } else {
+      for (int i = threadIdx.x; i < n; i += kTailThreads) xs[i] = (double)L.b[rperm[i]];
+      __syncthreads();
+      for (int k = 0; k < n; ++k) {
+        const double xk = xs[k];
+        for (int r = k + 1 + threadIdx.x; r < n; r += kTailThreads) xs[r] = xs[r] - lu[(int64_t)r * n + k] * xk;
+        __syncthreads();
+      }
+      for (int k = n - 1; k >= 0; --k) {
+        if (threadIdx.x == 0) xs[k] = xs[k] / lu[(int64_t)k * n + k];
+        __syncthreads();
+        const double xk = xs[k];
+        for (int r = threadIdx.x; r < k; r += kTailThreads) xs[r] = xs[r] - lu[(int64_t)r * n + k] * xk;
+        __syncthreads();
+      }
+      for (int i = threadIdx.x; i < n; i += kTailThreads) L.x[i] = (T)xs[i];
       __syncthreads();
     }
-    for (int k = n - 1; k >= 0; --k) {
-      if (threadIdx.x == 0) xs[k] = xs[k] / lu[(int64_t)k * n + k];
-      __syncthreads();
-      const double xk = xs[k];
-      for (int r = threadIdx.x; r < k; r += kTailThreads) xs[r] = xs[r] - lu[(int64_t)r * n + k] * xk;
-      __syncthreads();
-    }
-    for (int i = threadIdx.x; i < n; i += kTailThreads) L.x[i] = (T)xs[i];
-    __syncthreads();
   }
   // up: prolongation and post-smoothing
   for (int l = nlev - 2; l >= 0; --l) {
@@ -179,9 +193,11 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_vcycle(const TailLevel<T>
 
 template <typename T>
 void launch_tail_vcycle(const TailLevel<T>* levels, int nlev, int pre, int post, int32_t n_coarse, const double* lu,
-                        const int32_t* piv, hipStream_t s) {
-  hipLaunchKernelGGL((k_tail_vcycle<T>), dim3(1), dim3(kTailThreads), n_coarse * sizeof(double), s, levels, nlev, pre,
-                     post, n_coarse, lu, piv);
+                        const int32_t* rperm, hipStream_t s) {
+  const size_t lds = n_coarse <= kWave ? (kWave + (size_t)n_coarse * n_coarse) * sizeof(double)
+                                       : (size_t)n_coarse * sizeof(double);
+  hipLaunchKernelGGL((k_tail_vcycle<T>), dim3(1), dim3(kTailThreads), lds, s, levels, nlev, pre, post, n_coarse, lu,
+                     rperm);
   CPR_LAUNCH_CHECK();
 }
 template void launch_tail_vcycle<double>(const TailLevel<double>*, int, int, int, int32_t, const double*,

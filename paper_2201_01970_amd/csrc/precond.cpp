@@ -49,22 +49,20 @@ SellHost build_sell(const HostCsr& A, const std::vector<int32_t>& order, const s
 }
 
 // A level matrix on the device in the form its size and row lengths call for.
-// One lane per row (SELL-64) costs two ALU operations per entry but needs many
-// rows in flight to hide the gather latency of its sequential row walk; a lane
-// group per row (CSR) issues a whole row's loads at once, so small levels finish
-// in one memory round trip, at the price of the in-order broadcast sum.  SELL is
-// chosen when the matrix has at least kSellRows rows of at most kSellAvg entries
-// on average, lane groups otherwise (16 lanes up to 64 entries per row at the
-// maximum, 32 up to 128, else 64: one round of kChunks chunks per row).
-constexpr int32_t kSellRows = 100000;
-constexpr double kSellAvg = 40.0;
+// One lane per row (SELL-64) costs two ALU operations per entry and streams
+// perfectly, but walks each row serially, so it needs short rows and many rows
+// in flight; a 16-lane group per row (CSR) issues up to 64 entries of a row at
+// once, so long rows and small levels finish in one memory round trip, at the
+// price of the in-order broadcast sum.  Measured at 3.28M DOF on MI355X: SELL
+// wins on the finest levels (about 7 and 15 entries per row) and on P and R at
+// scale, 16-lane groups win on every Galerkin level with 30-90 entries per row
+// (about 2x faster than 32- or 64-lane groups) and on all small matrices.
+constexpr int32_t kSellRows = 32768;
+constexpr double kSellAvg = 20.0;
 
-int32_t layout_for(int32_t policy, int32_t n, double avg, int32_t maxlen) {
+int32_t layout_for(int32_t policy, int32_t n, double avg) {
   if (policy != 0) return policy;
-  if (n >= kSellRows && avg <= kSellAvg) return 1;
-  if (maxlen <= 64) return 16;
-  if (maxlen <= 128) return 32;
-  return 64;
+  return (n >= kSellRows && avg <= kSellAvg) ? 1 : 16;
 }
 
 template <typename T>
@@ -85,9 +83,7 @@ DevMat<T> upload_mat(Arena& ar, const HostCsr& A, const std::vector<int32_t>& or
   const int32_t n = static_cast<int32_t>(order.size());
   D.n_rows = n;
   const double avg = n > 0 ? static_cast<double>(A.nnz()) / n : 0.0;
-  int32_t maxlen = 0;
-  for (int32_t i = 0; i < A.n_rows; ++i) maxlen = std::max(maxlen, A.ptr[i + 1] - A.ptr[i]);
-  int32_t layout = layout_for(policy, n, avg, maxlen);
+  int32_t layout = layout_for(policy, n, avg);
   if (force_csr) layout = 16;
   if (layout == 1) {
     const SellHost S = build_sell(A, order, colmap);
@@ -197,7 +193,11 @@ class Precond final : public PrecondBase {
     }
     nL_ = lv_.back().n;
     lu_ = ar_.upload(lu);
-    piv_ = ar_.upload(piv);
+    // compose the factorisation's row swaps: (P b)_i = b[rperm[i]]
+    std::vector<int32_t> rperm(piv.size());
+    std::iota(rperm.begin(), rperm.end(), 0);
+    for (size_t k = 0; k < piv.size(); ++k) std::swap(rperm[k], rperm[piv[k]]);
+    piv_ = ar_.upload(rperm);
     // device descriptors of the tail levels
     std::vector<TailLevel<T>> td(nl - tail_);
     for (int l = tail_; l < nl; ++l) {
@@ -225,8 +225,7 @@ class Precond final : public PrecondBase {
         d.s1 = L.s1;
       }
     }
-    tail_dev_ = ar_.alloc<TailLevel<T>>(static_cast<int64_t>(td.size()));
-    HIPCHK(hipMemcpy(tail_dev_, td.data(), td.size() * sizeof(TailLevel<T>), hipMemcpyHostToDevice));
+    tail_dev_ = ar_.upload(td);
 
     // ---- fine level for stage 2: cells in block-colour order
     bcoff_ = bcoff;
@@ -268,11 +267,9 @@ class Precond final : public PrecondBase {
     fine_.col = ar_.upload(col);
     fine_.val = ar_.alloc<T>(slots * 9 * kWave);
     HIPCHK(hipMemsetAsync(fine_.val, 0, static_cast<size_t>(slots) * 9 * kWave * sizeof(T), s));
-    int64_t* d_pos = ar_.alloc<int64_t>(static_cast<int64_t>(pos.size()));
-    HIPCHK(hipMemcpy(d_pos, pos.data(), pos.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    int64_t* d_pos = ar_.upload(pos);
     launch_bsr_values_to_sell<T>(static_cast<int64_t>(pos.size()), d_vals_in, d_pos, fine_.val, s);
-    int64_t* d_diag_pos = ar_.alloc<int64_t>(n);
-    HIPCHK(hipMemcpy(d_diag_pos, diag_pos.data(), diag_pos.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    int64_t* d_diag_pos = ar_.upload(diag_pos);
     dinv_ld_ = n;
     dinv_ = ar_.alloc<T>(static_cast<int64_t>(9) * n);
     int32_t* d_sing = ar_.alloc<int32_t>(1);

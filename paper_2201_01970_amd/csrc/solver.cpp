@@ -9,6 +9,11 @@
 
 namespace cpr {
 
+std::mutex& device_api_mutex() {
+  static std::mutex m;
+  return m;
+}
+
 void hip_check(hipError_t e, const char* what, const char* file, int line) {
   if (e == hipSuccess) return;
   (void)hipGetLastError();
@@ -44,6 +49,7 @@ hipEvent_t Profiler::get_event() {
     return e;
   }
   hipEvent_t e;
+  std::lock_guard<std::mutex> lk(device_api_mutex());
   HIPCHK(hipEventCreate(&e));
   return e;
 }
@@ -118,7 +124,8 @@ void cpr_handle::build_precond() {
   const double t0 = now_ms();
   if (!h_vals_valid) {
     h_vals.resize(static_cast<size_t>(nnz_b) * 9);
-    HIPCHK(hipMemcpy(h_vals.data(), d_vals_in, h_vals.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(h_vals.data(), d_vals_in, h_vals.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
     h_vals_valid = true;
   }
   drop_graphs();
@@ -263,6 +270,32 @@ void cpr_handle::spmv(const double* x, double* y) {
   launch_bsr_spmv<double, double>(outer.view(), x, nullptr, y, stream);
 }
 
+// Capture step j once; returns null (and leaves no error behind) when the
+// runtime refuses the capture, in which case the step runs eagerly.
+hipGraphExec_t cpr_handle::capture_step(int j) {
+  std::lock_guard<std::mutex> lk(device_api_mutex());
+  if (!cap_stream) HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  bool ok = true;
+  try {
+    step_body(j, cap_stream);
+  } catch (const Error&) {
+    ok = false;
+  }
+  const hipError_t e_end = hipStreamEndCapture(cap_stream, &graph);
+  hipGraphExec_t exec = nullptr;
+  if (ok && e_end == hipSuccess && graph) {
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) exec = nullptr;
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipGetLastError();
+  return exec;
+}
+
 void cpr_handle::drop_graphs() {
   for (hipGraphExec_t& g : step_graph)
     if (g) (void)hipGraphExecDestroy(g);
@@ -369,19 +402,11 @@ cpr_status cpr_handle::solve(const double* b, double* x, double tol, cpr_solve_i
       for (int j = 0; j < m; ++j) {
         if (prm.use_graphs && !prof.on()) {
           if (step_graph.empty()) step_graph.assign(m, nullptr);
-          if (!step_graph[j]) {
-            if (!cap_stream) HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
-            hipGraph_t graph = nullptr;
-            HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
-            step_body(j, cap_stream);
-            HIPCHK(hipStreamEndCapture(cap_stream, &graph));
-            hipGraphExec_t exec = nullptr;
-            const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            HIPCHK(e);
-            step_graph[j] = exec;
-          }
-          HIPCHK(hipGraphLaunch(step_graph[j], stream));
+          if (!step_graph[j]) step_graph[j] = capture_step(j);
+          if (step_graph[j])
+            HIPCHK(hipGraphLaunch(step_graph[j], stream));
+          else
+            step_body(j, stream);  // capture was refused: same kernels, launched one by one
         } else {
           step_body(j, stream);
         }

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -25,6 +26,13 @@ struct Error : std::runtime_error {
 void hip_check(hipError_t e, const char* what, const char* file, int line);
 #define HIPCHK(x) ::cpr::hip_check((x), #x, __FILE__, __LINE__)
 
+// Graph capture on one thread is invalidated by device-synchronising runtime
+// calls (blocking copies, allocation and release, stream creation) issued by
+// another thread meanwhile.  Every such call of the library and every capture
+// holds this process-wide mutex, so handles used from different threads (the
+// serving runtime) never interfere.
+std::mutex& device_api_mutex();
+
 // Owns a list of device allocations.
 class Arena {
  public:
@@ -34,7 +42,11 @@ class Arena {
     if (n <= 0) n = 1;
     void* p = nullptr;
     const size_t bytes = static_cast<size_t>(n) * sizeof(T);
-    hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e;
+    {
+      std::lock_guard<std::mutex> lk(device_api_mutex());
+      e = hipMalloc(&p, bytes);
+    }
     if (e != hipSuccess) {
       (void)hipGetLastError();
       throw Error(CPR_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
@@ -46,10 +58,14 @@ class Arena {
   template <typename T>
   T* upload(const std::vector<T>& v) {
     T* p = alloc<T>(static_cast<int64_t>(v.size()));
-    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    if (!v.empty()) {
+      std::lock_guard<std::mutex> lk(device_api_mutex());
+      HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    }
     return p;
   }
   void release() {
+    std::lock_guard<std::mutex> lk(device_api_mutex());
     for (void* p : ptrs_) (void)hipFree(p);
     ptrs_.clear();
     bytes_ = 0;
@@ -175,6 +191,7 @@ struct cpr_handle {
   hipStream_t cap_stream = nullptr;
   void drop_graphs();
   void step_body(int j, hipStream_t s);
+  hipGraphExec_t capture_step(int j);
 
   void build_precond();
   cpr_status solve(const double* b, double* x, double tol, cpr_solve_info* info);

@@ -24,7 +24,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="HIP library not
 
 def _declared_symbols():
     names = set()
-    for h in ("cpr.h", "cpr_inspect.h"):
+    for h in ("cpr.h", "cpr_inspect.h", "cpr_serve.h"):
         text = open(os.path.join(ROOT, "include", h)).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
         for m in re.finditer(r"\b(cpr_[a-z0-9_]+)\s*\(", text):
