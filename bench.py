@@ -34,12 +34,13 @@ def _pct(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def cpu_baseline(shape_full, gpu_its, n_full):
+def cpu_baseline(workload, shape_full, gpu_its, n_full):
     """Time the oracle (single thread) on a slab of the same workload and scale.
 
-    The sample is the same generator with nz = 4 (about 51K active cells):
-    oracle SETUP + FP64 CPR-FGMRES to 1e-6.  The reported value scales the
-    oracle's solve time per iteration per cell to the full grid and to the
+    The sample is the workload's own generator on a thin slab (nz = 4, about
+    51K cells for the SPE10-sized grid; nx, ny halved for the channelised
+    grid): oracle SETUP + FP64 CPR-FGMRES to 1e-6.  The reported value scales
+    the oracle's solve time per iteration per cell to the full grid and to the
     GPU's FP64 iteration count.
     """
     from threadpoolctl import threadpool_limits
@@ -50,9 +51,14 @@ def cpu_baseline(shape_full, gpu_its, n_full):
     from oracle import fgmres as ofg
     from workloads import blackoil as bo
 
-    shape = (shape_full[0], shape_full[1], 4)
-    case = bo.case_spe10_like(seed=1100, shape=shape)
-    b = bo.rhs(case.ndof, 1101)
+    if workload == "channels":
+        shape = (shape_full[0] // 2, shape_full[1] // 2, 4)
+        case = bo.case_channels(seed=1400, shape=shape)
+        b = bo.rhs(case.ndof, 1401)
+    else:
+        shape = (shape_full[0], shape_full[1], 4)
+        case = bo.case_spe10_like(seed=1100, shape=shape)
+        b = bo.rhs(case.ndof, 1101)
     with threadpool_limits(limits=1):
         A = ocpr.Bsr.from_case(case)
         t0 = time.perf_counter()
@@ -86,33 +92,286 @@ def _cpu_name():
     return "unknown"
 
 
+def _gen_request(desc):
+    """Worker-process job: materialise one serving request (numpy only)."""
+    from workloads import blackoil as bo
+
+    case, b = bo.serving_case(desc)
+    return desc["req"], desc["case_id"], case.row_ptr, case.col, case.vals, b
+
+
+def serve_bench(args):
+    """Serving stream: Poisson arrivals of solve requests of mixed sizes.
+
+    Requests follow the serving-stream recipe (1e4-1e6 cells, random aspect,
+    30% repeat Newton steps of resident cases).  A saturation pass over the
+    first requests (all submitted at once) fixes the service rate; the timed
+    pass submits every request at Poisson arrival times with rate
+    lambda = 0.8 x saturated throughput and reports p50/p99 latency from
+    arrival to completion and the completed solves per second.
+    """
+    import multiprocessing as mp
+    import threading
+
+    import numpy as np
+
+    from workloads import blackoil as bo
+
+    # worker processes are forked before anything touches the GPU
+    pool = mp.get_context("fork").Pool(processes=args.gen_procs)
+    descs = bo.serving_requests(n_req=args.requests, seed=1300)
+
+    import torch  # noqa: F401  (initialises the device in this process only)
+
+    from paper_2201_01970_amd import Params, Server
+
+    params = Params(precond_fp32=True)
+    budget = int(args.budget_gb * (1 << 30))
+
+    def run_pass(sub_descs, rate):
+        srv = Server(budget, args.slots, params)
+        it = pool.imap(_gen_request, sub_descs, chunksize=1)
+        rng = np.random.default_rng(1301)
+        t0 = time.perf_counter()
+        arrivals = []
+        t_next = 0.0
+        tickets = []
+        lock = threading.Lock()
+        results = {}
+
+        def waiter():
+            while True:
+                with lock:
+                    item = tickets.pop(0) if tickets else None
+                if item is None:
+                    if done_submitting.is_set():
+                        with lock:
+                            if not tickets:
+                                return
+                    time.sleep(0.001)
+                    continue
+                req, ticket, keep = item
+                x, info = srv.wait(ticket)
+                results[req] = (info, time.perf_counter() - t0)
+
+        done_submitting = threading.Event()
+        th = threading.Thread(target=waiter)
+        th.start()
+        for req, case_id, rp, col, vals, b in it:
+            if rate:
+                t_next += rng.exponential(1.0 / rate)
+                delay = t0 + t_next - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            t_sub = time.perf_counter() - t0
+            ticket = srv.submit(case_id, rp, col, vals, b, tol=args.tol)
+            with lock:
+                tickets.append((req, ticket, (rp, col, vals, b)))
+            arrivals.append(t_sub)
+        done_submitting.set()
+        th.join()
+        wall = time.perf_counter() - t0
+        stats = srv.stats()
+        srv.close()
+        return results, arrivals, wall, stats
+
+    n_sat = min(args.saturation_requests, len(descs))
+    res_sat, _, wall_sat, _ = run_pass(descs[:n_sat], None)
+    sat_rate = n_sat / wall_sat
+    rate = args.rate if args.rate else 0.8 * sat_rate
+    print(f"[serve] saturation: {n_sat} requests in {wall_sat:.1f}s = {sat_rate:.2f}/s; lambda = {rate:.2f}/s",
+          file=sys.stderr, flush=True)
+    res, arrivals, wall, stats = run_pass(descs, rate)
+    pool.close()
+    lat = [info["latency_ms"] for info, _ in res.values()]
+    ok = [info for info, _ in res.values() if info["status"] == "CPR_OK"]
+    its = [info["iterations"] for info in ok]
+    rel = [info["relres_true"] for info in ok]
+    out = {
+        "metric": "serving p50/p99 latency (arrival to completion), solves/s",
+        "value": _pct(lat, 0.5), "unit": "ms", "higher_is_better": False,
+        "p50_ms": _pct(lat, 0.5), "p90_ms": _pct(lat, 0.9), "p99_ms": _pct(lat, 0.99),
+        "solves_per_s": len(ok) / wall, "lambda_per_s": rate, "saturated_per_s": sat_rate,
+        "requests": len(descs), "completed_ok": len(ok), "wall_s": wall,
+        "iterations_median": _pct(its, 0.5), "relres_true_max": max(rel) if rel else None,
+        "rebuilt": sum(1 for info in ok if info["rebuilt"]),
+        "server": stats, "slots": args.slots, "budget_gb": args.budget_gb,
+        "config": {"workload": "serving stream: 1e4-1e6 cells log-uniform, nz 2-50, aspect 1/4-4, "
+                               "sigma U[1,2.5], 30% repeat Newton steps (+-5% drift)",
+                   "precond": "fp32", "outer": "fp64 FGMRES(30)", "tol": args.tol},
+        "data": "synthetic",
+    }
+    print(json.dumps(out), flush=True)
+
+
+KERNEL_NAMES = {
+    0: "bsr_spmv_fp64", 1: "pgs_scm_colour_sweep_level0", 2: "residual_restrict_prolong_level0",
+    3: "stage2_block_gs", 4: "pgs_scm_colour_sweep_coarse", 5: "residual_restrict_prolong_coarse",
+    6: "tail_vcycle_one_workgroup",
+}
+KERNEL_SOURCES = {
+    "bsr_spmv_fp64": "kernels_fine.hip", "stage2_block_gs": "kernels_fine.hip",
+    "pgs_scm_colour_sweep_level0": "kernels_amg.hip", "pgs_scm_colour_sweep_coarse": "kernels_amg.hip",
+    "residual_restrict_prolong_level0": "kernels_amg.hip", "residual_restrict_prolong_coarse": "kernels_amg.hip",
+    "tail_vcycle_one_workgroup": "kernels_tail.hip",
+}
+
+
+def _source_hash(fname):
+    import hashlib
+
+    path = os.path.join(ROOT, "paper_2201_01970_amd", "csrc", fname)
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current source of the kernel (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    rec = data.get(kernel)
+    if not rec or rec.get("source_sha256_16") != _source_hash(KERNEL_SOURCES[kernel]):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def _params(args, **kw):
+    from paper_2201_01970_amd import Params
+
+    if getattr(args, "tail_nnz", None) is not None:
+        kw["tail_nnz"] = args.tail_nnz
+    if getattr(args, "row_layout", None) is not None:
+        kw["row_layout"] = args.row_layout
+    return Params(**kw)
+
+
+def _case_for(args):
+    from workloads import blackoil as bo
+
+    if args.workload == "channels":
+        shape = tuple(args.shape) if args.shape else (200, 200, 100)
+        case = bo.case_channels(seed=1400, shape=shape)
+        b = bo.rhs(case.ndof, 1401)
+        desc = (f"channelised black-oil Jacobian {shape[0]}x{shape[1]}x{shape[2]}, 1000 mD sinusoidal channels "
+                f"on 1 mD, kz/kx=0.01")
+    else:
+        shape = tuple(args.shape) if args.shape else (60, 220, 85)
+        case = bo.case_spe10_like(seed=1100, shape=shape)
+        b = bo.rhs(case.ndof, 1101)
+        desc = (f"spe10-like black-oil Jacobian {shape[0]}x{shape[1]}x{shape[2]}, 2.5% inactive, "
+                f"layered lognormal sigma=2, kz/kx=0.1")
+    return shape, case, b, desc
+
+
+def newton_bench(args):
+    """Newton sequence: 12 Jacobians with a fixed pattern and +-5% value drift per
+    step on the SPE10-sized grid; adaptive SETUP with the relative rule
+    (rebuild when iterations exceed 1.3x those of the last SETUP), FP64 and FP32
+    preconditioners; per step: iterations, rebuild flag, true relres, times."""
+    import torch
+
+    from paper_2201_01970_amd import Params, Solver
+    from workloads import blackoil as bo
+
+    shape = tuple(args.shape) if args.shape else (60, 220, 85)
+    steps = list(bo.newton_sequence(n_steps=args.newton_steps, shape=shape))
+    dev = torch.device("cuda:0")
+    out = {"metric": "Newton sequence: SetupCalls, iterations, time", "config": {
+        "workload": f"spe10-like {shape[0]}x{shape[1]}x{shape[2]}, {len(steps)} Jacobians, +-5% drift per step",
+        "rule": "rebuild iff It > 1.3 It_ref", "tol": args.tol}, "data": "synthetic"}
+    for fp32 in (False, True):
+        rows = []
+        c0 = steps[0][1]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S = Solver(torch.as_tensor(c0.row_ptr, device=dev), torch.as_tensor(c0.col, device=dev),
+                   torch.as_tensor(c0.vals.reshape(-1), device=dev), Params(precond_fp32=fp32))
+        torch.cuda.synchronize()
+        first_setup = time.perf_counter() - t0
+        total = first_setup
+        for k, case, b_np in steps:
+            vals = torch.as_tensor(case.vals.reshape(-1), device=dev)
+            b = torch.as_tensor(b_np, device=dev)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            if k > 0:
+                S.update_values(vals)
+            x, info = S.solve(b, tol=args.tol)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            total += dt
+            rows.append({"step": k, "iterations": info["iterations"], "rebuilt": bool(info["rebuilt"]) or k == 0,
+                         "relres_true": info["relres_true"], "setup_ms": info["setup_ms"] if k else first_setup * 1e3,
+                         "solve_ms": info["solve_ms"], "step_ms": dt * 1e3})
+            print(f"[newton fp32={fp32}] step {k}: its={info['iterations']} rebuilt={info['rebuilt']} "
+                  f"relres={info['relres_true']:.2e} {dt*1e3:.1f} ms", file=sys.stderr, flush=True)
+        S.close()
+        key = "fp32" if fp32 else "fp64"
+        setup_ms = sum(r["setup_ms"] for r in rows if r["rebuilt"])
+        out[key] = {"steps": rows, "setup_calls": sum(1 for r in rows if r["rebuilt"]),
+                    "iterations_total": sum(r["iterations"] for r in rows), "total_s": total,
+                    "setup_ratio": setup_ms / 1e3 / total, "max_relres": max(r["relres_true"] for r in rows)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--shape", type=int, nargs=3, default=(60, 220, 85))
+    ap.add_argument("--shape", type=int, nargs=3, default=None)
+    ap.add_argument("--workload", choices=("spe10", "channels"), default="spe10")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibrate", action="store_true",
+                    help="launch a 1 GiB plain copy kernel three times first (counter calibration)")
+    ap.add_argument("--newton", action="store_true", help="run the Newton-sequence benchmark instead")
+    ap.add_argument("--newton-steps", type=int, default=12)
+    ap.add_argument("--serve", action="store_true", help="run the serving-stream benchmark instead")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--saturation-requests", type=int, default=64)
+    ap.add_argument("--rate", type=float, default=0.0, help="arrival rate per second (default 0.8 x saturation)")
+    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--gen-procs", type=int, default=12)
+    ap.add_argument("--tail-nnz", type=int, default=None, help="override Params.tail_nnz")
+    ap.add_argument("--row-layout", type=int, default=None, help="override Params.row_layout")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solve of one Jacobian is not "
               "sharded across GPUs in this build", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve_bench(args)
+        return
+    if args.newton:
+        newton_bench(args)
+        return
 
     import numpy as np
     import torch
 
     from paper_2201_01970_amd import Params, Solver
     from paper_2201_01970_amd import _capi as capi
-    from workloads import blackoil as bo
 
     dev = torch.device("cuda:0")
-    shape = tuple(args.shape)
+    if args.copy_calibrate:
+        import ctypes
+
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            capi.check(capi.lib().cpr_copy_kernel(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                                  nbytes, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        del src, dst
     t0 = time.perf_counter()
-    case = bo.case_spe10_like(seed=1100, shape=shape)
-    b_np = bo.rhs(case.ndof, 1101)
+    shape, case, b_np, workload = _case_for(args)
     gen_s = time.perf_counter() - t0
     rp = torch.as_tensor(case.row_ptr, device=dev)
     col = torch.as_tensor(case.col, device=dev)
@@ -124,7 +383,7 @@ def main():
     def run(fp32, steps, warmup, profile=False):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        S = Solver(rp, col, vals, Params(precond_fp32=fp32))
+        S = Solver(rp, col, vals, _params(args, precond_fp32=fp32))
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t
         x = torch.zeros_like(b)
@@ -160,9 +419,12 @@ def main():
             prof = {k: S.profile_read(k) for k in range(capi.CPR_KSTAT_COUNT)}
             prof["total_ms"] = prof_total_ms
         levels = [S.level_info(l) for l in range(S.level_info(0)["n_levels"])]
+        for l, lv in enumerate(levels):
+            rl = np.diff(S.level_arrays(l)["row_ptr"])
+            lv["row_max"] = int(rl.max()) if rl.size else 0
+            lv["row_p90"] = float(np.percentile(rl, 90)) if rl.size else 0.0
         S.close()
-        return dict(setup_s=setup_s, times=times, total_ms=total_ms, info=info, prof=prof, levels=levels,
-                    x=x)
+        return dict(setup_s=setup_s, times=times, total_ms=total_ms, info=info, prof=prof, levels=levels)
 
     r32 = run(True, args.steps, args.warmup, profile=True)
     print(f"[bench] fp32 precond: its={r32['info']['iterations']} relres={r32['info']['relres_true']:.2e} "
@@ -175,8 +437,6 @@ def main():
               f"median={statistics.median(r64['times']):.2f} ms setup={r64['setup_s']:.1f}s",
               file=sys.stderr, flush=True)
 
-    names = {capi.CPR_KSTAT_SPMV: "bsr_spmv_fp64", capi.CPR_KSTAT_SMOOTH_L0: "pgs_scm_colour_sweep_level0",
-             capi.CPR_KSTAT_TRANSFER_L0: "residual_restrict_prolong_level0", capi.CPR_KSTAT_STAGE2: "stage2_block_gs"}
     kernels = {}
     prof_total = r32["prof"].pop("total_ms")
     for k, (n, ms, by) in r32["prof"].items():
@@ -184,15 +444,15 @@ def main():
             continue
         avg_ms = ms / n
         gbs = by / n / (avg_ms * 1e-3) / 1e9
-        kernels[names[k]] = {"launches": n, "avg_us": avg_ms * 1e3, "bytes_per_launch": by / n,
-                             "achieved_GBs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
-                             "share_of_profiled_solves": ms / prof_total}
+        kernels[KERNEL_NAMES[k]] = {"launches": n, "avg_us": avg_ms * 1e3, "bytes_per_launch": by / n,
+                                    "achieved_GBs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+                                    "share_of_profiled_solves": ms / prof_total}
     dom = max(kernels, key=lambda k: kernels[k]["share_of_profiled_solves"]) if kernels else None
     roof = None
     if dom:
         d = kernels[dom]
         roof = {"bound": "hbm", "kernel": dom, "achieved": d["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": d["achieved_GBs"] / HBM_PEAK_GBS, "traffic": None}
+                "frac": d["achieved_GBs"] / HBM_PEAK_GBS, "traffic": _measured_traffic(dom)}
 
     med32 = statistics.median(r32["times"])
     out = {
@@ -208,11 +468,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 preconditioner / f64 FGMRES",
         "data": "synthetic",
-        "config": {"workload": f"spe10-like black-oil Jacobian {shape[0]}x{shape[1]}x{shape[2]}, "
-                               f"2.5% inactive, layered lognormal sigma=2, kz/kx=0.1",
-                   "n_cells": case.n_b, "dof": case.ndof, "nnz_blocks": case.nnz_b, "tol": args.tol,
-                   "krylov": "FGMRES(30)", "amg": "RS theta=0.25, coarse<=50, PGS-SCM theta=0.05, 2+2 sweeps",
-                   "stage2": "multi-colour block GS"},
+        "config": {"workload": workload, "n_cells": case.n_b, "dof": case.ndof, "nnz_blocks": case.nnz_b,
+                   "tol": args.tol, "krylov": "FGMRES(30)",
+                   "amg": "RS theta=0.25, coarse<=50, PGS-SCM theta=0.05, 2+2 sweeps",
+                   "stage2": "multi-colour block GS",
+                   "tail_nnz": _params(args).tail_nnz, "row_layout": _params(args).row_layout},
         "p50_ms": _pct(r32["times"], 0.5),
         "p99_ms": _pct(r32["times"], 0.99),
         "iterations_fp32": r32["info"]["iterations"],
@@ -220,6 +480,8 @@ def main():
         "setup_s_fp32": r32["setup_s"],
         "levels": [lv["n"] for lv in r32["levels"]],
         "colours": [lv["n_colours"] for lv in r32["levels"]],
+        "level_nnz": [lv["nnz"] for lv in r32["levels"]],
+        "level_row_p90_max": [[lv["row_p90"], lv["row_max"]] for lv in r32["levels"]],
         "roofline": roof,
         "kernels": kernels,
     }
@@ -230,7 +492,7 @@ def main():
                     "setup_s_fp64": r64["setup_s"], "speedup_fp32_vs_fp64": med64 / med32})
     if not args.no_cpu_baseline:
         its = r64["info"]["iterations"] if r64 else r32["info"]["iterations"]
-        out["cpu_baseline"] = cpu_baseline(shape, its, case.n_b)
+        out["cpu_baseline"] = cpu_baseline(args.workload, shape, its, case.n_b)
     print(json.dumps(out), flush=True)
 
 

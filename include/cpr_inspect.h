@@ -101,11 +101,14 @@ cpr_status cpr_host_galerkin(int32_t n, int32_t n_coarse, const int32_t* a_ptr, 
 /* Kernel classes timed with HIP events on the handle's stream while
  * profiling is enabled. */
 enum {
-  CPR_KSTAT_SPMV = 0,       /* outer FP64 BSR product */
-  CPR_KSTAT_SMOOTH_L0 = 1,  /* PGS-SCM colour sweeps of level 0 */
-  CPR_KSTAT_TRANSFER_L0 = 2,/* level-0 residual + restriction + prolongation */
-  CPR_KSTAT_STAGE2 = 3,     /* stage-2 block Gauss-Seidel colour kernels */
-  CPR_KSTAT_COUNT = 4
+  CPR_KSTAT_SPMV = 0,           /* outer FP64 BSR product */
+  CPR_KSTAT_SMOOTH_L0 = 1,      /* PGS-SCM colour sweeps of level 0 */
+  CPR_KSTAT_TRANSFER_L0 = 2,    /* level-0 residual + restriction + prolongation */
+  CPR_KSTAT_STAGE2 = 3,         /* stage-2 block Gauss-Seidel colour kernels */
+  CPR_KSTAT_SMOOTH_COARSE = 4,  /* PGS-SCM colour sweeps of levels 1.. (outside the tail) */
+  CPR_KSTAT_TRANSFER_COARSE = 5,/* residual + restriction + prolongation of levels 1.. */
+  CPR_KSTAT_TAIL = 6,           /* the one-workgroup V-cycle of the smallest levels */
+  CPR_KSTAT_COUNT = 7
 };
 
 /* enable != 0: record a HIP event pair around every launch of the kernel

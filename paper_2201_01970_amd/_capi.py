@@ -30,7 +30,10 @@ CPR_KSTAT_SPMV = 0
 CPR_KSTAT_SMOOTH_L0 = 1
 CPR_KSTAT_TRANSFER_L0 = 2
 CPR_KSTAT_STAGE2 = 3
-CPR_KSTAT_COUNT = 4
+CPR_KSTAT_SMOOTH_COARSE = 4
+CPR_KSTAT_TRANSFER_COARSE = 5
+CPR_KSTAT_TAIL = 6
+CPR_KSTAT_COUNT = 7
 
 
 class cpr_bsr(C.Structure):

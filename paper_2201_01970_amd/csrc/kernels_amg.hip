@@ -5,10 +5,12 @@
 //  * SELL-64, one lane per row (short rows: the finest level, P, R).  Slots
 //    are fetched kUnroll at a time so the gathers of a row overlap.
 //  * CSR with a group of 16, 32 or 64 lanes per row (long rows of the
-//    Galerkin levels).  Each lane fetches one stored entry of a chunk (four
-//    chunks in flight) and forms its product; the group then adds the
-//    products in stored order, broadcast one lane at a time (through the
-//    scalar unit when the group is the whole wavefront).
+//    Galerkin levels).  Each lane fetches one stored entry of a chunk (up to
+//    eight chunks in flight, as many as the row needs) and forms its product;
+//    the group then adds the products in stored order.  A 16-lane group is
+//    one DPP row: the running value moves one lane to the right per step
+//    (register moves only, no LDS), so the last lane ends with the sequential
+//    result.  Wider groups broadcast one lane at a time.
 // Either way every row is accumulated exactly as a sequential loop over its
 // stored entries would (products rounded, then added in order), so results
 // match a sequential implementation bit for bit.  Entries that do not
@@ -18,7 +20,7 @@
 namespace cpr {
 
 constexpr int kUnroll = 8;
-constexpr int kChunks = 4;  // chunks of a row whose loads are issued together
+constexpr int kChunks = 8;  // chunks of a row whose loads may be issued together
 
 // ------------------------------------------------------------------ helpers
 // Row q of a SELL matrix: call f(col, val) for each stored entry in order,
@@ -63,6 +65,22 @@ __device__ __forceinline__ T group_ordered(T s, T p) {
     s = SUB ? (s - v) : (s + v);
   }
   return s;
+}
+
+// One chunk of a group's ordered accumulation: s (op) p_0 (op) ... (op) p_{G-1}.
+// Addition runs as subtraction of the negated product (a + b and a - (-b) are
+// the same IEEE operation).  The result is valid in lane last_lane<G>().
+template <int G>
+__device__ __forceinline__ constexpr int last_lane() {
+  return G == 16 ? 15 : 0;
+}
+template <typename T, int G, bool SUB>
+__device__ __forceinline__ T group_chunk(T s, T p, int lane) {
+  if constexpr (G == 16) {
+    return row_chain_sub<T>(s, SUB ? p : -p, lane);
+  } else {
+    return group_ordered<T, G, SUB>(s, p);
+  }
 }
 
 // ------------------------------------------------------------------ colour sweep
@@ -112,6 +130,8 @@ __global__ __launch_bounds__(kBlock) void k_gs_grp(int32_t lo, int32_t hi, const
   T s = b[q];
   const int32_t p0 = rp[q], p1 = rp[q + 1];
   for (int32_t p = p0; p < p1; p += G * kChunks) {
+    // chunks this row still has (uniform across the group)
+    const int nch = min(kChunks, (p1 - p + G - 1) / G);
     int32_t c[kChunks];
     T a[kChunks], prod[kChunks];
 #pragma unroll
@@ -127,9 +147,10 @@ __global__ __launch_bounds__(kBlock) void k_gs_grp(int32_t lo, int32_t hi, const
       prod[u] = use ? a[u] * xv : (T)0;
     }
 #pragma unroll
-    for (int u = 0; u < kChunks; ++u) s = group_ordered<T, G, true>(s, prod[u]);
+    for (int u = 0; u < kChunks; ++u)
+      if (u < nch) s = group_chunk<T, G, true>(s, prod[u], lane);
   }
-  if (lane == 0) {
+  if (lane == last_lane<G>()) {
     const T xn = s / diag[q];
     x[q] = xn;
     s_out[q] = xn;
@@ -216,6 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_grp(int32_t n, const int32_t* _
   T acc = (MODE == 0) ? b[q] : (T)0;
   const int32_t p0 = rp[q], p1 = rp[q + 1];
   for (int32_t p = p0; p < p1; p += G * kChunks) {
+    const int nch = min(kChunks, (p1 - p + G - 1) / G);
     int32_t c[kChunks];
     T a[kChunks], prod[kChunks];
 #pragma unroll
@@ -227,9 +249,10 @@ __global__ __launch_bounds__(kBlock) void k_rows_grp(int32_t n, const int32_t* _
 #pragma unroll
     for (int u = 0; u < kChunks; ++u) prod[u] = (c[u] >= 0) ? a[u] * x[c[u]] : (T)0;
 #pragma unroll
-    for (int u = 0; u < kChunks; ++u) acc = group_ordered<T, G, MODE == 0>(acc, prod[u]);
+    for (int u = 0; u < kChunks; ++u)
+      if (u < nch) acc = group_chunk<T, G, MODE == 0>(acc, prod[u], lane);
   }
-  if (lane == 0) finish_row<T, MODE>(q, acc, b, y, snap);
+  if (lane == last_lane<G>()) finish_row<T, MODE>(q, acc, b, y, snap);
 }
 
 template <typename T, int MODE>

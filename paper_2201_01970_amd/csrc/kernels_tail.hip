@@ -7,8 +7,8 @@
 // the dense coarsest LU solve, prolongation and post-sweeps — inside one
 // workgroup of 1024 threads, with a workgroup barrier between dependent
 // phases instead of a kernel boundary.  The arithmetic is exactly that of the
-// per-colour kernels: each row is summed by a group of kTailGroup lanes in
-// stored order (products broadcast one lane at a time), so the results are
+// per-colour kernels: each row is summed by a 16-lane group in stored order
+// (the running value carried lane to lane by DPP moves), so the results are
 // bit-identical to theirs.
 #include "kernels_common.hpp"
 
@@ -19,18 +19,8 @@ constexpr int kTailGroup = 16;
 constexpr int kTailRows = kTailThreads / kTailGroup;
 constexpr int kTailChunks = 4;  // chunks of a row whose loads are issued together
 
-template <typename T>
-__device__ __forceinline__ T tail_ordered_sub(T s, T p) {
-#pragma unroll
-  for (int k = 0; k < kTailGroup; ++k) s = s - __shfl(p, k, kTailGroup);
-  return s;
-}
-template <typename T>
-__device__ __forceinline__ T tail_ordered_add(T s, T p) {
-#pragma unroll
-  for (int k = 0; k < kTailGroup; ++k) s = s + __shfl(p, k, kTailGroup);
-  return s;
-}
+static_assert(kTailGroup == 16, "the ordered row sums use one DPP row per group");
+constexpr int kTailLast = kTailGroup - 1;  // lane that ends with a row's sum
 
 // One colour of a sweep over rows [lo, hi) (see k_gs_grp for the semantics).
 template <typename T>
@@ -55,10 +45,12 @@ __device__ void tail_colour(const TailLevel<T>& L, int32_t lo, int32_t hi, const
         if (use) xv = zero ? L.x[c[u]] : ((c[u] >= lo && c[u] < hi) ? s_in[c[u]] : L.x[c[u]]);
         prod[u] = use ? a[u] * xv : (T)0;
       }
+      const int nch = min(kTailChunks, (p1 - p + kTailGroup - 1) / kTailGroup);
 #pragma unroll
-      for (int u = 0; u < kTailChunks; ++u) s = tail_ordered_sub(s, prod[u]);
+      for (int u = 0; u < kTailChunks; ++u)
+        if (u < nch) s = row_chain_sub<T>(s, prod[u], lane);
     }
-    if (lane == 0) {
+    if (lane == kTailLast) {
       const T xn = s / L.diag[q];
       L.x[q] = xn;
       s_out[q] = xn;
@@ -85,11 +77,12 @@ __device__ void tail_rows(int32_t n, const int32_t* rp, const int32_t* col, cons
       }
 #pragma unroll
       for (int u = 0; u < kTailChunks; ++u) prod[u] = (c[u] >= 0) ? a[u] * x[c[u]] : (T)0;
+      const int nch = min(kTailChunks, (p1 - p + kTailGroup - 1) / kTailGroup);
 #pragma unroll
       for (int u = 0; u < kTailChunks; ++u)
-        acc = (MODE == 0) ? tail_ordered_sub(acc, prod[u]) : tail_ordered_add(acc, prod[u]);
+        if (u < nch) acc = row_chain_sub<T>(acc, MODE == 0 ? prod[u] : -prod[u], lane);
     }
-    if (lane == 0) {
+    if (lane == kTailLast) {
       if (MODE == 2) {
         const T yn = y[q] + acc;
         y[q] = yn;

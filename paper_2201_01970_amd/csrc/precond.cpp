@@ -226,6 +226,14 @@ class Precond final : public PrecondBase {
       }
     }
     tail_dev_ = ar_.upload(td);
+    tail_bytes_ = 0.0;
+    for (int l = tail_; l + 1 < nl; ++l) {
+      const Level& L = lv_[l];
+      const double sweep = L.nnz * (sv + 4.0) + 4.0 * L.n + 4.0 * L.n * sv;
+      tail_bytes_ += (pre_ + post_) * sweep + L.nnz * (sv + 4) + 4.0 * L.n + 3.0 * L.n * sv +
+                     (L.nnz_r + L.nnz_p) * (sv + 4.0) + 4.0 * (L.n + lv_[l + 1].n) + 4.0 * L.n * sv;
+    }
+    tail_bytes_ += 8.0 * nL_ * nL_;
 
     // ---- fine level for stage 2: cells in block-colour order
     bcoff_ = bcoff;
@@ -326,11 +334,11 @@ class Precond final : public PrecondBase {
     Level& L = lv_[l];
     T* S[2] = {L.s0, L.s1};
     const MatView<T> A = L.A.view();
+    const int kind = l == 0 ? CPR_KSTAT_SMOOTH_L0 : CPR_KSTAT_SMOOTH_COARSE;
     for (size_t c = 0; c + 1 < L.coff.size(); ++c) {
-      const bool timed = timer && l == 0;
-      if (timed) timer->begin(CPR_KSTAT_SMOOTH_L0, s);
+      if (timer) timer->begin(kind, s);
       launch_gs_colour<T>(A, L.diag, L.coff[c], L.coff[c + 1], L.b, L.x, S[cur], S[cur ^ 1], zero, s);
-      if (timed) timer->end(CPR_KSTAT_SMOOTH_L0, s, L.colour_bytes[c]);
+      if (timer) timer->end(kind, s, L.colour_bytes[c]);
     }
   }
 
@@ -338,7 +346,9 @@ class Precond final : public PrecondBase {
     Level& L = lv_[l];
     const int nl = static_cast<int>(lv_.size());
     if (l == tail_) {
+      if (timer) timer->begin(CPR_KSTAT_TAIL, s);
       launch_tail_vcycle<T>(tail_dev_, nl - tail_, pre_, post_, nL_, lu_, piv_, s);
+      if (timer) timer->end(CPR_KSTAT_TAIL, s, tail_bytes_);
       return;
     }
     const double sv = sizeof(T);
@@ -349,18 +359,18 @@ class Precond final : public PrecondBase {
       cur ^= 1;
     }
     Level& C = lv_[l + 1];
-    const bool timed = timer && l == 0;
-    if (timed) timer->begin(CPR_KSTAT_TRANSFER_L0, s);
+    const int kind = l == 0 ? CPR_KSTAT_TRANSFER_L0 : CPR_KSTAT_TRANSFER_COARSE;
+    if (timer) timer->begin(kind, s);
     launch_csr_residual<T>(L.A.view(), L.b, L.x, L.r, s);
-    if (timed) timer->end(CPR_KSTAT_TRANSFER_L0, s, L.nnz * (sv + 4) + 4.0 * L.n + 3.0 * L.n * sv);
-    if (timed) timer->begin(CPR_KSTAT_TRANSFER_L0, s);
+    if (timer) timer->end(kind, s, L.nnz * (sv + 4) + 4.0 * L.n + 3.0 * L.n * sv);
+    if (timer) timer->begin(kind, s);
     launch_csr_spmv<T>(L.R.view(), L.r, C.b, s);
-    if (timed) timer->end(CPR_KSTAT_TRANSFER_L0, s, L.nnz_r * (sv + 4) + 4.0 * C.n + L.n * sv + C.n * sv);
+    if (timer) timer->end(kind, s, L.nnz_r * (sv + 4) + 4.0 * C.n + L.n * sv + C.n * sv);
     vcycle(l + 1, s);
     T* S[2] = {L.s0, L.s1};
-    if (timed) timer->begin(CPR_KSTAT_TRANSFER_L0, s);
+    if (timer) timer->begin(kind, s);
     launch_prolong_add<T>(L.P.view(), C.x, L.x, S[cur], s);
-    if (timed) timer->end(CPR_KSTAT_TRANSFER_L0, s, L.nnz_p * (sv + 4) + 4.0 * L.n + C.n * sv + 2.0 * L.n * sv);
+    if (timer) timer->end(kind, s, L.nnz_p * (sv + 4) + 4.0 * L.n + C.n * sv + 2.0 * L.n * sv);
     for (int w = 0; w < post_; ++w) {
       sweep(l, cur, false, s);
       cur ^= 1;
@@ -371,6 +381,7 @@ class Precond final : public PrecondBase {
   std::vector<Level> lv_;
   int tail_ = 0;
   TailLevel<T>* tail_dev_ = nullptr;
+  double tail_bytes_ = 0.0;
   int pre_, post_;
   int32_t n_b_;
   int32_t nL_ = 0;
