@@ -36,7 +36,8 @@ struct SellView {
 template <typename T>
 struct MatView {
   int32_t n_rows = 0;
-  int32_t group = 1;
+  int32_t group = 1;   // 1: SELL-64, one lane per row; 16/32/64: CSR, lanes per row
+  int32_t depth = 8;   // requests in flight per row: SELL slots (8, 16, 32) or CSR chunks of `group` (4, 8, 16)
   const int32_t* ptr = nullptr;
   const int32_t* col = nullptr;
   const T* val = nullptr;
@@ -102,9 +103,13 @@ void launch_csr_spmv(const MatView<T>& A, const T* x, T* y, hipStream_t s);
 template <typename T>
 void launch_prolong_add(const MatView<T>& P, const T* e, T* x, T* snap, hipStream_t s);
 
-// Device-resident description of one level handled by the one-workgroup tail
-// V-cycle (all matrices CSR, rows in colour order; P maps the next level to
-// this one, R this level to the next).
+// One level of the one-workgroup tail of the V-cycle.  Matrices stay in
+// device memory (CSR, rows in colour order); the level's vectors x, b, r and
+// the two sweep snapshots live in LDS for the whole kernel, at element offsets
+// off_* from the start of the vector area.  The first tail level reads b from
+// gb when the kernel starts and writes x to gx when it ends (its parent level
+// restricts into gb and prolongates from gx).  P interpolates from the next
+// level to this one, R restricts this level to the next.
 template <typename T>
 struct TailLevel {
   int32_t n = 0, ncol = 0;
@@ -115,15 +120,27 @@ struct TailLevel {
   const T* p_val = nullptr;
   const int32_t *r_rp = nullptr, *r_col = nullptr;
   const T* r_val = nullptr;
-  T *x = nullptr, *b = nullptr, *r = nullptr, *s0 = nullptr, *s1 = nullptr;
+  int32_t off_x = 0, off_b = 0, off_r = 0, off_s0 = 0, off_s1 = 0;
+  T* gx = nullptr;
+  const T* gb = nullptr;
 };
+
+// LDS layout of the tail: the coarsest solve's FP64 staging first, then the
+// level vectors.  tail_lds_doubles: doubles of the staging for a coarsest level
+// of n_coarse rows; the vector area starts at that many doubles.
+__host__ __device__ inline int64_t tail_lds_doubles(int32_t n_coarse) {
+  return n_coarse <= 64 ? 64 + static_cast<int64_t>(n_coarse) * n_coarse : n_coarse;
+}
 
 // V-cycle of the levels levels[0..nlev-1] (the last one the coarsest, solved
 // with the FP64 LU factors of P A = L U, rperm[i] = source row of row i of P b)
-// in one workgroup; levels[0].b is the input and levels[0].x the output.
+// in one workgroup with lds_bytes of dynamic LDS.
 template <typename T>
 void launch_tail_vcycle(const TailLevel<T>* levels, int nlev, int pre, int post, int32_t n_coarse, const double* lu,
-                        const int32_t* rperm, hipStream_t s);
+                        const int32_t* rperm, size_t lds_bytes, hipStream_t s);
+
+// Largest dynamic LDS a workgroup of the tail kernel may use on the current device.
+size_t tail_lds_limit();
 
 // ---- setup kernel: strength masks (bit 1: RS strength, bit 2: eq. (strong-matrix))
 void launch_strength(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, double theta_rs,

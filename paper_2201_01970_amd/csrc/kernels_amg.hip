@@ -4,9 +4,13 @@
 // Two storage forms, chosen per matrix at SETUP from its row lengths:
 //  * SELL-64, one lane per row (short rows: the finest level, P, R).  Slots
 //    are fetched kUnroll at a time so the gathers of a row overlap.
+//  * Quad-vector CSR (the Galerkin levels): four lanes per row, rows padded
+//    to a multiple of four entries, each lane reading four contiguous entries
+//    per chunk with one vector load (see quad_row_sub); sixteen rows per
+//    wavefront.
 //  * CSR with a group of 16, 32 or 64 lanes per row (long rows of the
-//    Galerkin levels).  Each lane fetches one stored entry of a chunk (up to
-//    eight chunks in flight, as many as the row needs) and forms its product;
+//    Galerkin levels).  Each lane fetches one stored entry of a chunk (4, 8 or
+//    16 chunks in flight, as many as the row needs) and forms its product;
 //    the group then adds the products in stored order.  A 16-lane group is
 //    one DPP row: the running value moves one lane to the right per step
 //    (register moves only, no LDS), so the last lane ends with the sequential
@@ -19,29 +23,28 @@
 
 namespace cpr {
 
-constexpr int kUnroll = 8;
-constexpr int kChunks = 8;  // chunks of a row whose loads may be issued together
-
 // ------------------------------------------------------------------ helpers
 // Row q of a SELL matrix: call f(col, val) for each stored entry in order,
-// with the loads of kUnroll consecutive slots issued together.
-template <typename T, typename F>
+// with the loads of U consecutive slots issued together (U is chosen per
+// matrix from its slice widths, so most rows take one batch: every further
+// batch costs two dependent memory round trips).
+template <typename T, int U, typename F>
 __device__ __forceinline__ void sell_row(int32_t q, const int32_t* __restrict__ slice_ptr,
                                          const int32_t* __restrict__ col, const T* __restrict__ val, F&& f) {
   const int32_t slice = q >> 6, lane = q & 63;
   const int32_t t0 = slice_ptr[slice], t1 = slice_ptr[slice + 1];
-  for (int32_t t = t0; t < t1; t += kUnroll) {
-    int32_t c[kUnroll];
-    T a[kUnroll];
+  for (int32_t t = t0; t < t1; t += U) {
+    int32_t c[U];
+    T a[U];
     // columns and values are requested together: padded slots hold value 0
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int64_t e = (int64_t)(t + u) * kWave + lane;
       c[u] = (t + u < t1) ? col[e] : kPadCol;
       a[u] = (t + u < t1) ? val[e] : (T)0;
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) f(c[u], a[u]);
+    for (int u = 0; u < U; ++u) f(c[u], a[u]);
   }
 }
 
@@ -87,16 +90,21 @@ __device__ __forceinline__ T group_chunk(T s, T p, int lane) {
 // One colour [lo, hi): x_i = (b_i - sum_{j != i} a_ij xt_j) / a_ii with xt_j =
 // s_in[j] for j in [lo, hi) (the colour's values before this colour started)
 // and x[j] otherwise; ZERO: x == 0 on entry, so only j < lo contribute.
+// The product a_ij xt_j of one stored entry, 0 where it does not contribute
+// (padding, the diagonal, and in ZERO mode every column of this colour or a
+// later one).  Branch-free: an entry that does not contribute reads row q's
+// own value (a valid address) and its product is replaced by 0.
 template <typename T, bool ZERO>
-__device__ __forceinline__ T gs_value(int32_t q, int32_t c, int32_t lo, int32_t hi, const T* __restrict__ x,
-                                      const T* __restrict__ s_in, bool& use) {
-  use = c >= 0 && c != q && (!ZERO || c < lo);
-  if (!use) return (T)0;
-  if (ZERO) return x[c];
-  return (c >= lo && c < hi) ? s_in[c] : x[c];
+__device__ __forceinline__ T gs_prod(int32_t q, int32_t c, T a, int32_t lo, int32_t hi, const T* __restrict__ x,
+                                     const T* __restrict__ s_in) {
+  const bool use = c >= 0 && c != q && (!ZERO || c < lo);
+  const int32_t cc = use ? c : q;
+  const T* src = (!ZERO && cc >= lo && cc < hi) ? s_in : x;
+  const T xv = src[cc];
+  return use ? a * xv : (T)0;
 }
 
-template <typename T, bool ZERO>
+template <typename T, int U, bool ZERO>
 __global__ __launch_bounds__(kBlock) void k_gs_sell(int32_t lo, int32_t hi, const int32_t* __restrict__ slice_ptr,
                                                     const int32_t* __restrict__ col, const T* __restrict__ val,
                                                     const T* __restrict__ diag, const T* __restrict__ b,
@@ -106,48 +114,45 @@ __global__ __launch_bounds__(kBlock) void k_gs_sell(int32_t lo, int32_t hi, cons
   const int32_t q = base + xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (q < lo || q >= hi) return;
   T s = b[q];
-  sell_row<T>(q, slice_ptr, col, val, [&](int32_t c, T a) {
-    bool use;
-    const T xv = gs_value<T, ZERO>(q, c, lo, hi, x, s_in, use);
-    const T prod = use ? a * xv : (T)0;
-    s = s - prod;
-  });
+  sell_row<T, U>(q, slice_ptr, col, val, [&](int32_t c, T a) { s = s - gs_prod<T, ZERO>(q, c, a, lo, hi, x, s_in); });
   const T xn = s / diag[q];
   x[q] = xn;
   s_out[q] = xn;
 }
 
-template <typename T, int G, bool ZERO>
+// CH chunks of G entries of a row are requested together (chosen per matrix
+// from its row lengths so that most rows take one pass).
+template <typename T, int G, int CH, bool ZERO>
 __global__ __launch_bounds__(kBlock) void k_gs_grp(int32_t lo, int32_t hi, const int32_t* __restrict__ rp,
                                                    const int32_t* __restrict__ col, const T* __restrict__ val,
                                                    const T* __restrict__ diag, const T* __restrict__ b,
                                                    T* __restrict__ x, const T* __restrict__ s_in,
                                                    T* __restrict__ s_out) {
-  const int32_t g = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
+  // Rows of a colour are stored longest first, so neighbouring workgroups carry
+  // similar work: the hardware's round-robin of workgroups over the XCDs then
+  // gives every XCD an even share (a contiguous range per XCD would hand one
+  // XCD all the longest rows).  The vectors of these levels fit every L2.
+  const int32_t g = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int lane = threadIdx.x % G;
   const int32_t q = lo + g;
   if (q >= hi) return;
   T s = b[q];
   const int32_t p0 = rp[q], p1 = rp[q + 1];
-  for (int32_t p = p0; p < p1; p += G * kChunks) {
+  for (int32_t p = p0; p < p1; p += G * CH) {
     // chunks this row still has (uniform across the group)
-    const int nch = min(kChunks, (p1 - p + G - 1) / G);
-    int32_t c[kChunks];
-    T a[kChunks], prod[kChunks];
+    const int nch = min(CH, (p1 - p + G - 1) / G);
+    int32_t c[CH];
+    T a[CH], prod[CH];
 #pragma unroll
-    for (int u = 0; u < kChunks; ++u) {
+    for (int u = 0; u < CH; ++u) {
       const int32_t e = p + u * G + lane;
       c[u] = (e < p1) ? col[e] : kPadCol;
       a[u] = (e < p1) ? val[e] : (T)0;
     }
 #pragma unroll
-    for (int u = 0; u < kChunks; ++u) {
-      bool use;
-      const T xv = gs_value<T, ZERO>(q, c[u], lo, hi, x, s_in, use);
-      prod[u] = use ? a[u] * xv : (T)0;
-    }
+    for (int u = 0; u < CH; ++u) prod[u] = gs_prod<T, ZERO>(q, c[u], a[u], lo, hi, x, s_in);
 #pragma unroll
-    for (int u = 0; u < kChunks; ++u)
+    for (int u = 0; u < CH; ++u)
       if (u < nch) s = group_chunk<T, G, true>(s, prod[u], lane);
   }
   if (lane == last_lane<G>()) {
@@ -157,36 +162,93 @@ __global__ __launch_bounds__(kBlock) void k_gs_grp(int32_t lo, int32_t hi, const
   }
 }
 
+template <typename T, int G, int CH>
+void launch_gs_grp(const MatView<T>& A, const T* diag, int32_t lo, int32_t hi, const T* b, T* x, const T* s_in,
+                   T* s_out, bool zero_start, hipStream_t s) {
+  const int grid = div_up((int64_t)(hi - lo) * G, kBlock);
+  if (zero_start)
+    hipLaunchKernelGGL((k_gs_grp<T, G, CH, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag,
+                       b, x, s_in, s_out);
+  else
+    hipLaunchKernelGGL((k_gs_grp<T, G, CH, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag,
+                       b, x, s_in, s_out);
+}
+
+// Quad-vector CSR colour sweep: a quad per row (rows of a colour are stored
+// longest first, so neighbouring workgroups carry similar work and the
+// hardware's round-robin over the XCDs balances them).
+template <typename T, int CH, bool ZERO>
+__global__ __launch_bounds__(kBlock) void k_gs_q4(int32_t lo, int32_t hi, const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                  const T* __restrict__ diag, const T* __restrict__ b,
+                                                  T* __restrict__ x, const T* __restrict__ s_in,
+                                                  T* __restrict__ s_out) {
+  const int32_t q = lo + (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 2);
+  const int lane = threadIdx.x & 3;
+  if (q >= hi) return;
+  const T s = quad_row_sub<T, CH>(b[q], rp[q], rp[q + 1], col, val, lane,
+                                  [&](int32_t c, T a) { return gs_prod<T, ZERO>(q, c, a, lo, hi, x, s_in); });
+  if (lane == 3) {
+    const T xn = s / diag[q];
+    x[q] = xn;
+    s_out[q] = xn;
+  }
+}
+
+template <typename T, int CH>
+void launch_gs_q4(const MatView<T>& A, const T* diag, int32_t lo, int32_t hi, const T* b, T* x, const T* s_in,
+                  T* s_out, bool zero_start, hipStream_t s) {
+  const int grid = div_up((int64_t)(hi - lo) * 4, kBlock);
+  if (zero_start)
+    hipLaunchKernelGGL((k_gs_q4<T, CH, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag, b,
+                       x, s_in, s_out);
+  else
+    hipLaunchKernelGGL((k_gs_q4<T, CH, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag, b,
+                       x, s_in, s_out);
+}
+
+template <typename T, int U>
+void launch_gs_sell(const MatView<T>& A, const T* diag, int32_t lo, int32_t hi, const T* b, T* x, const T* s_in,
+                    T* s_out, bool zero_start, hipStream_t s) {
+  const int32_t base = lo & ~63;
+  const int grid = div_up(hi - base, kBlock);
+  if (zero_start)
+    hipLaunchKernelGGL((k_gs_sell<T, U, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag, b,
+                       x, s_in, s_out);
+  else
+    hipLaunchKernelGGL((k_gs_sell<T, U, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag, b,
+                       x, s_in, s_out);
+}
+
 template <typename T>
 void launch_gs_colour(const MatView<T>& A, const T* diag, int32_t lo, int32_t hi, const T* b, T* x, const T* s_in,
                       T* s_out, bool zero_start, hipStream_t s) {
   if (hi <= lo) return;
   if (A.group == 1) {
-    const int32_t base = lo & ~63;
-    const int grid = div_up(hi - base, kBlock);
-    if (zero_start)
-      hipLaunchKernelGGL((k_gs_sell<T, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag, b,
-                         x, s_in, s_out);
+    if (A.depth <= 8)
+      launch_gs_sell<T, 8>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
+    else if (A.depth <= 16)
+      launch_gs_sell<T, 16>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
     else
-      hipLaunchKernelGGL((k_gs_sell<T, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag,
-                         b, x, s_in, s_out);
+      launch_gs_sell<T, 32>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
+  } else if (A.group == 4) {
+    if (A.depth <= 2)
+      launch_gs_q4<T, 2>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
+    else if (A.depth <= 4)
+      launch_gs_q4<T, 4>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
+    else
+      launch_gs_q4<T, 8>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
+  } else if (A.group == 16) {
+    if (A.depth <= 4)
+      launch_gs_grp<T, 16, 4>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
+    else if (A.depth <= 8)
+      launch_gs_grp<T, 16, 8>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
+    else
+      launch_gs_grp<T, 16, 16>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
+  } else if (A.group == 32) {
+    launch_gs_grp<T, 32, 4>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
   } else {
-    const int grid = div_up((int64_t)(hi - lo) * A.group, kBlock);
-#define CPR_GS_GRP(G)                                                                                         \
-  if (zero_start)                                                                                             \
-    hipLaunchKernelGGL((k_gs_grp<T, G, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag, \
-                       b, x, s_in, s_out);                                                                     \
-  else                                                                                                        \
-    hipLaunchKernelGGL((k_gs_grp<T, G, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val,     \
-                       diag, b, x, s_in, s_out);
-    if (A.group == 16) {
-      CPR_GS_GRP(16)
-    } else if (A.group == 32) {
-      CPR_GS_GRP(32)
-    } else {
-      CPR_GS_GRP(64)
-    }
-#undef CPR_GS_GRP
+    launch_gs_grp<T, 64, 4>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
   }
   CPR_LAUNCH_CHECK();
 }
@@ -211,7 +273,7 @@ __device__ __forceinline__ void finish_row(int32_t q, T acc, const T* __restrict
   }
 }
 
-template <typename T, int MODE>
+template <typename T, int U, int MODE>
 __global__ __launch_bounds__(kBlock) void k_rows_sell(int32_t n, const int32_t* __restrict__ slice_ptr,
                                                       const int32_t* __restrict__ col, const T* __restrict__ val,
                                                       const T* __restrict__ b, const T* __restrict__ x,
@@ -219,57 +281,102 @@ __global__ __launch_bounds__(kBlock) void k_rows_sell(int32_t n, const int32_t* 
   const int32_t q = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (q >= n) return;
   T acc = (MODE == 0) ? b[q] : (T)0;
-  sell_row<T>(q, slice_ptr, col, val, [&](int32_t c, T a) {
+  sell_row<T, U>(q, slice_ptr, col, val, [&](int32_t c, T a) {
     const T prod = (c >= 0) ? a * x[c] : (T)0;
     acc = (MODE == 0) ? (acc - prod) : (acc + prod);
   });
   finish_row<T, MODE>(q, acc, b, y, snap);
 }
 
-template <typename T, int G, int MODE>
+template <typename T, int G, int CH, int MODE>
 __global__ __launch_bounds__(kBlock) void k_rows_grp(int32_t n, const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ col, const T* __restrict__ val,
                                                      const T* __restrict__ b, const T* __restrict__ x,
                                                      T* __restrict__ y, T* __restrict__ snap) {
-  const int32_t q = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
+  const int32_t q = (blockIdx.x * kBlock + threadIdx.x) / G;  // round-robin over XCDs, as k_gs_grp
   const int lane = threadIdx.x % G;
   if (q >= n) return;
   T acc = (MODE == 0) ? b[q] : (T)0;
   const int32_t p0 = rp[q], p1 = rp[q + 1];
-  for (int32_t p = p0; p < p1; p += G * kChunks) {
-    const int nch = min(kChunks, (p1 - p + G - 1) / G);
-    int32_t c[kChunks];
-    T a[kChunks], prod[kChunks];
+  for (int32_t p = p0; p < p1; p += G * CH) {
+    const int nch = min(CH, (p1 - p + G - 1) / G);
+    int32_t c[CH];
+    T a[CH], prod[CH];
 #pragma unroll
-    for (int u = 0; u < kChunks; ++u) {
+    for (int u = 0; u < CH; ++u) {
       const int32_t e = p + u * G + lane;
       c[u] = (e < p1) ? col[e] : kPadCol;
       a[u] = (e < p1) ? val[e] : (T)0;
     }
 #pragma unroll
-    for (int u = 0; u < kChunks; ++u) prod[u] = (c[u] >= 0) ? a[u] * x[c[u]] : (T)0;
+    for (int u = 0; u < CH; ++u) prod[u] = (c[u] >= 0) ? a[u] * x[c[u]] : (T)0;
 #pragma unroll
-    for (int u = 0; u < kChunks; ++u)
+    for (int u = 0; u < CH; ++u)
       if (u < nch) acc = group_chunk<T, G, MODE == 0>(acc, prod[u], lane);
   }
   if (lane == last_lane<G>()) finish_row<T, MODE>(q, acc, b, y, snap);
 }
 
+template <typename T, int CH, int MODE>
+__global__ __launch_bounds__(kBlock) void k_rows_q4(int32_t n, const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                    const T* __restrict__ b, const T* __restrict__ x,
+                                                    T* __restrict__ y, T* __restrict__ snap) {
+  const int32_t q = (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 2);
+  const int lane = threadIdx.x & 3;
+  if (q >= n) return;
+  // MODE 1 and 2 add: subtract the negated products (the same IEEE operation)
+  const T acc = quad_row_sub<T, CH>((MODE == 0) ? b[q] : (T)0, rp[q], rp[q + 1], col, val, lane,
+                                    [&](int32_t c, T a) {
+                                      const T pr = (c >= 0) ? a * x[c] : (T)0;
+                                      return MODE == 0 ? pr : -pr;
+                                    });
+  if (lane == 3) finish_row<T, MODE>(q, acc, b, y, snap);
+}
+
+template <typename T, int CH, int MODE>
+void launch_rows_q4(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, hipStream_t s) {
+  hipLaunchKernelGGL((k_rows_q4<T, CH, MODE>), dim3(div_up((int64_t)A.n_rows * 4, kBlock)), dim3(kBlock), 0, s,
+                     A.n_rows, A.ptr, A.col, A.val, b, x, y, snap);
+}
+
+template <typename T, int G, int CH, int MODE>
+void launch_rows_grp(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, hipStream_t s) {
+  hipLaunchKernelGGL((k_rows_grp<T, G, CH, MODE>), dim3(div_up((int64_t)A.n_rows * G, kBlock)), dim3(kBlock), 0, s,
+                     A.n_rows, A.ptr, A.col, A.val, b, x, y, snap);
+}
+
+template <typename T, int U, int MODE>
+void launch_rows_sell(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, hipStream_t s) {
+  hipLaunchKernelGGL((k_rows_sell<T, U, MODE>), dim3(div_up(A.n_rows, kBlock)), dim3(kBlock), 0, s, A.n_rows, A.ptr,
+                     A.col, A.val, b, x, y, snap);
+}
+
 template <typename T, int MODE>
 void launch_rows(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, hipStream_t s) {
   if (A.n_rows == 0) return;
-  if (A.group == 1)
-    hipLaunchKernelGGL((k_rows_sell<T, MODE>), dim3(div_up(A.n_rows, kBlock)), dim3(kBlock), 0, s, A.n_rows, A.ptr,
-                       A.col, A.val, b, x, y, snap);
+  if (A.group == 1 && A.depth <= 8)
+    launch_rows_sell<T, 8, MODE>(A, b, x, y, snap, s);
+  else if (A.group == 1 && A.depth <= 16)
+    launch_rows_sell<T, 16, MODE>(A, b, x, y, snap, s);
+  else if (A.group == 1)
+    launch_rows_sell<T, 32, MODE>(A, b, x, y, snap, s);
+  else if (A.group == 4 && A.depth <= 2)
+    launch_rows_q4<T, 2, MODE>(A, b, x, y, snap, s);
+  else if (A.group == 4 && A.depth <= 4)
+    launch_rows_q4<T, 4, MODE>(A, b, x, y, snap, s);
+  else if (A.group == 4)
+    launch_rows_q4<T, 8, MODE>(A, b, x, y, snap, s);
+  else if (A.group == 16 && A.depth <= 4)
+    launch_rows_grp<T, 16, 4, MODE>(A, b, x, y, snap, s);
+  else if (A.group == 16 && A.depth <= 8)
+    launch_rows_grp<T, 16, 8, MODE>(A, b, x, y, snap, s);
   else if (A.group == 16)
-    hipLaunchKernelGGL((k_rows_grp<T, 16, MODE>), dim3(div_up((int64_t)A.n_rows * 16, kBlock)), dim3(kBlock), 0, s,
-                       A.n_rows, A.ptr, A.col, A.val, b, x, y, snap);
+    launch_rows_grp<T, 16, 16, MODE>(A, b, x, y, snap, s);
   else if (A.group == 32)
-    hipLaunchKernelGGL((k_rows_grp<T, 32, MODE>), dim3(div_up((int64_t)A.n_rows * 32, kBlock)), dim3(kBlock), 0, s,
-                       A.n_rows, A.ptr, A.col, A.val, b, x, y, snap);
+    launch_rows_grp<T, 32, 4, MODE>(A, b, x, y, snap, s);
   else
-    hipLaunchKernelGGL((k_rows_grp<T, 64, MODE>), dim3(div_up((int64_t)A.n_rows * 64, kBlock)), dim3(kBlock), 0, s,
-                       A.n_rows, A.ptr, A.col, A.val, b, x, y, snap);
+    launch_rows_grp<T, 64, 4, MODE>(A, b, x, y, snap, s);
   CPR_LAUNCH_CHECK();
 }
 

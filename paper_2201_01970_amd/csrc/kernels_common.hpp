@@ -25,6 +25,11 @@ inline int div_up(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / 
 // each row (lane 0 reads lane 15).
 constexpr int kDppRowShr1 = 0x111;
 constexpr int kDppRowRor1 = 0x121;
+// quad_perm controls: lane i of each quad reads the lane given by bits
+// [2i+1:2i].  [3,0,1,2] rotates right by one; [0,0,1,2] shifts right by one
+// with lane 0 reading itself.
+constexpr int kDppQuadRor1 = 3 | (0 << 2) | (1 << 4) | (2 << 6);
+constexpr int kDppQuadShr1 = 0 | (0 << 2) | (1 << 4) | (2 << 6);
 
 // A lane's value moved by a DPP control; a lane without a source keeps its own.
 template <int CTRL>
@@ -55,6 +60,120 @@ __device__ __forceinline__ T row_chain_sub(T s, T p, int lane) {
   s = dpp_move<kDppRowRor1>(s) - p;
 #pragma unroll
   for (int k = 1; k < 16; ++k) s = dpp_move<kDppRowShr1>(s) - pk;
+  return s;
+}
+
+// The same ordered subtraction over one chunk of a 4-lane group (one quad):
+// lane 3 holds the running value on entry and (((s - p_0) - p_1) - p_2) - p_3
+// on return.
+template <typename T>
+__device__ __forceinline__ T quad_chain_sub(T s, T p, int lane) {
+  const T pk = lane == 0 ? (T)0 : p;
+  s = dpp_move<kDppQuadRor1>(s) - p;
+  s = dpp_move<kDppQuadShr1>(s) - pk;
+  s = dpp_move<kDppQuadShr1>(s) - pk;
+  s = dpp_move<kDppQuadShr1>(s) - pk;
+  return s;
+}
+
+// Loads through a pointer known to address device memory (global address
+// space), for pointers the compiler cannot classify itself (read from a
+// descriptor in memory): keeps them off the generic path, whose loads are
+// counted with LDS operations and so serialise with them.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> gmem(const T* p) {
+  return (gptr<T>)p;
+}
+
+// Four consecutive entries starting at a multiple of four (16-byte aligned
+// columns, 16- or 32-byte aligned values) as one or two vector loads.
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void load4_cols(const int32_t* col, int32_t e, int32_t c[4]) {
+  const i32x4 v = *reinterpret_cast<const i32x4*>(col + e);
+  c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+}
+__device__ __forceinline__ void load4_cols(gptr<int32_t> col, int32_t e, int32_t c[4]) {
+  const i32x4 v = *(gptr<i32x4>)(col + e);
+  c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+}
+__device__ __forceinline__ void load4_vals(const float* val, int32_t e, float a[4]) {
+  const f32x4 v = *reinterpret_cast<const f32x4*>(val + e);
+  a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
+}
+__device__ __forceinline__ void load4_vals(gptr<float> val, int32_t e, float a[4]) {
+  const f32x4 v = *(gptr<f32x4>)(val + e);
+  a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
+}
+__device__ __forceinline__ void load4_vals(const double* val, int32_t e, double a[4]) {
+  const f64x2 v0 = *reinterpret_cast<const f64x2*>(val + e);
+  const f64x2 v1 = *reinterpret_cast<const f64x2*>(val + e + 2);
+  a[0] = v0.x; a[1] = v0.y; a[2] = v1.x; a[3] = v1.y;
+}
+__device__ __forceinline__ void load4_vals(gptr<double> val, int32_t e, double a[4]) {
+  const f64x2 v0 = *(gptr<f64x2>)(val + e);
+  const f64x2 v1 = *(gptr<f64x2>)(val + e + 2);
+  a[0] = v0.x; a[1] = v0.y; a[2] = v1.x; a[3] = v1.y;
+}
+
+// Row sum of a quad-vector CSR matrix taken by the four lanes of a quad.
+// Rows are padded to a multiple of four stored entries (padding: column -1,
+// value 0).  Chunk u of a pass covers entries [p + 16u, p + 16u + 16): lane k
+// holds the four entries p + 16u + 4k .. + 3 (one vector load each for
+// columns and values), so a quad reads whole 64-byte segments.  prod(c, a)
+// gives the product of one entry (0 where the entry does not contribute,
+// which leaves every running value unchanged).  The products are subtracted
+// from s in stored order: lane 0 continues from lane 3's running value
+// (rotate) and subtracts its four products; then, three times, each lane
+// continues from its left neighbour and subtracts its four (lane 0 subtracts
+// zeros, so it keeps its value; a lane recomputing an already final value
+// reproduces it), so lane 3 holds the chunk's result, rounded exactly as a
+// sequential loop over the row rounds it.  CH chunks are requested at once.
+template <typename T, int CH, typename ColP, typename ValP, typename Prod>
+__device__ __forceinline__ T quad_row_sub(T s, int32_t p0, int32_t p1, ColP col, ValP val, int lane,
+                                          Prod&& prod) {
+  for (int32_t p = p0; p < p1; p += 16 * CH) {
+    const int nch = min(CH, (p1 - p + 15) / 16);  // uniform across the quad
+    int32_t c[CH][4];
+    T a[CH][4];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int32_t e = p + 16 * u + 4 * lane;
+      if (e < p1) {
+        load4_cols(col, e, c[u]);
+        load4_vals(val, e, a[u]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          c[u][k] = -1;
+          a[u][k] = (T)0;
+        }
+      }
+    }
+    T pr[CH][4];
+#pragma unroll
+    for (int u = 0; u < CH; ++u)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) pr[u][k] = prod(c[u][k], a[u][k]);
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      if (u < nch) {
+        s = dpp_move<kDppQuadRor1>(s);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s = s - pr[u][k];
+#pragma unroll
+        for (int step = 1; step < 4; ++step) {
+          s = dpp_move<kDppQuadShr1>(s);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) s = s - (lane == 0 ? (T)0 : pr[u][k]);
+        }
+      }
+    }
+  }
   return s;
 }
 

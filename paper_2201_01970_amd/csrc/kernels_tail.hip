@@ -1,88 +1,79 @@
 // The coarse end of the pressure V-cycle in one workgroup.
 //
-// On the small coarse levels every kernel of the V-cycle is bound by launch
-// and memory latency, not bandwidth: a colour of a level with a few thousand
-// rows moves well under a megabyte.  This kernel runs the whole V-cycle of
-// the levels [first, last] — PGS-SCM pre-sweeps, residual, restriction,
-// the dense coarsest LU solve, prolongation and post-sweeps — inside one
-// workgroup of 1024 threads, with a workgroup barrier between dependent
-// phases instead of a kernel boundary.  The arithmetic is exactly that of the
-// per-colour kernels: each row is summed by a 16-lane group in stored order
-// (the running value carried lane to lane by DPP moves), so the results are
-// bit-identical to theirs.
+// On the small coarse levels every per-colour kernel is bound by launch and
+// memory latency, not bandwidth: a colour of a level with a few hundred rows
+// moves a few hundred kilobytes.  This kernel runs the whole V-cycle of the
+// levels [first, last] — PGS-SCM pre-sweeps, residual, restriction, the dense
+// coarsest LU solve, prolongation and post-sweeps — inside one workgroup of
+// 1024 threads, with a workgroup barrier between dependent phases instead of a
+// kernel boundary.  Every vector of these levels stays in LDS for the whole
+// kernel, so a phase's gathers and writes never leave the compute unit; the
+// matrices are read from device memory (they stay in L2 across the sweeps).
+//
+// Rows are taken by quads in the quad-vector CSR layout (256 rows per pass;
+// see quad_row_sub): every row sum is accumulated in stored order and rounded
+// exactly as a sequential loop rounds it, so the results are bit-identical to
+// those of the per-colour kernels.  Matrix pointers come from a descriptor in
+// memory and are read through gmem (global loads); the level vectors are LDS.
 #include "kernels_common.hpp"
 
 namespace cpr {
 
 constexpr int kTailThreads = 1024;
-constexpr int kTailGroup = 16;
-constexpr int kTailRows = kTailThreads / kTailGroup;
-constexpr int kTailChunks = 4;  // chunks of a row whose loads are issued together
-
-static_assert(kTailGroup == 16, "the ordered row sums use one DPP row per group");
-constexpr int kTailLast = kTailGroup - 1;  // lane that ends with a row's sum
-
-// One colour of a sweep over rows [lo, hi) (see k_gs_grp for the semantics).
+constexpr int kTailRows = kTailThreads / 4;  // rows per pass
+// chunks of 16 entries a quad requests at once (fewer in FP64: a 1024-thread
+// workgroup leaves 128 registers per lane)
 template <typename T>
-__device__ void tail_colour(const TailLevel<T>& L, int32_t lo, int32_t hi, const T* s_in, T* s_out, bool zero) {
-  const int lane = threadIdx.x % kTailGroup;
-  for (int32_t q = lo + (int32_t)threadIdx.x / kTailGroup; q < hi; q += kTailRows) {
-    T s = L.b[q];
-    const int32_t p0 = L.a_rp[q], p1 = L.a_rp[q + 1];
-    for (int32_t p = p0; p < p1; p += kTailGroup * kTailChunks) {
-      int32_t c[kTailChunks];
-      T a[kTailChunks], prod[kTailChunks];
-#pragma unroll
-      for (int u = 0; u < kTailChunks; ++u) {
-        const int32_t e = p + u * kTailGroup + lane;
-        c[u] = (e < p1) ? L.a_col[e] : -1;
-        a[u] = (e < p1) ? L.a_val[e] : (T)0;
-      }
-#pragma unroll
-      for (int u = 0; u < kTailChunks; ++u) {
-        const bool use = c[u] >= 0 && c[u] != q && (!zero || c[u] < lo);
-        T xv = (T)0;
-        if (use) xv = zero ? L.x[c[u]] : ((c[u] >= lo && c[u] < hi) ? s_in[c[u]] : L.x[c[u]]);
-        prod[u] = use ? a[u] * xv : (T)0;
-      }
-      const int nch = min(kTailChunks, (p1 - p + kTailGroup - 1) / kTailGroup);
-#pragma unroll
-      for (int u = 0; u < kTailChunks; ++u)
-        if (u < nch) s = row_chain_sub<T>(s, prod[u], lane);
-    }
-    if (lane == kTailLast) {
-      const T xn = s / L.diag[q];
-      L.x[q] = xn;
+constexpr int tail_chunks() {
+  return sizeof(T) == 4 ? 8 : 4;
+}
+
+// One colour [lo, hi) of a sweep (semantics of k_gs_grp).
+template <typename T>
+__device__ __forceinline__ void tail_colour(const TailLevel<T>& L, T* V, int32_t lo, int32_t hi, const T* s_in,
+                                            T* s_out, bool zero) {
+  const int lane = threadIdx.x & 3;
+  T* x = V + L.off_x;
+  const T* b = V + L.off_b;
+  const auto rp = gmem(L.a_rp);
+  const auto col = gmem(L.a_col);
+  const auto val = gmem(L.a_val);
+  for (int32_t q = lo + (int32_t)(threadIdx.x >> 2); q < hi; q += kTailRows) {
+    // branch-free gather: an entry that does not contribute reads row q's own
+    // value and its product is replaced by 0
+    const T s = quad_row_sub<T, tail_chunks<T>()>(b[q], rp[q], rp[q + 1], col, val, lane, [&](int32_t c, T a) {
+      const bool use = c >= 0 && c != q && (!zero || c < lo);
+      const int32_t cc = use ? c : q;
+      const T* src = (!zero && cc >= lo && cc < hi) ? s_in : x;
+      const T xv = src[cc];
+      return use ? a * xv : (T)0;
+    });
+    if (lane == 3) {
+      const T xn = s / gmem(L.diag)[q];
+      x[q] = xn;
       s_out[q] = xn;
     }
   }
 }
 
 // MODE 0: y = b - A x;  MODE 1: y = A x;  MODE 2: y += A x and snap = y.
+// b, x, y, snap are LDS arrays; the matrix is in device memory.
 template <typename T, int MODE>
-__device__ void tail_rows(int32_t n, const int32_t* rp, const int32_t* col, const T* val, const T* b, const T* x,
-                          T* y, T* snap) {
-  const int lane = threadIdx.x % kTailGroup;
-  for (int32_t q = (int32_t)threadIdx.x / kTailGroup; q < n; q += kTailRows) {
-    T acc = (MODE == 0) ? b[q] : (T)0;
-    const int32_t p0 = rp[q], p1 = rp[q + 1];
-    for (int32_t p = p0; p < p1; p += kTailGroup * kTailChunks) {
-      int32_t c[kTailChunks];
-      T a[kTailChunks], prod[kTailChunks];
-#pragma unroll
-      for (int u = 0; u < kTailChunks; ++u) {
-        const int32_t e = p + u * kTailGroup + lane;
-        c[u] = (e < p1) ? col[e] : -1;
-        a[u] = (e < p1) ? val[e] : (T)0;
-      }
-#pragma unroll
-      for (int u = 0; u < kTailChunks; ++u) prod[u] = (c[u] >= 0) ? a[u] * x[c[u]] : (T)0;
-      const int nch = min(kTailChunks, (p1 - p + kTailGroup - 1) / kTailGroup);
-#pragma unroll
-      for (int u = 0; u < kTailChunks; ++u)
-        if (u < nch) acc = row_chain_sub<T>(acc, MODE == 0 ? prod[u] : -prod[u], lane);
-    }
-    if (lane == kTailLast) {
+__device__ __forceinline__ void tail_rows(int32_t n, const int32_t* rp_, const int32_t* col_, const T* val_,
+                                          const T* b, const T* x, T* y, T* snap) {
+  const int lane = threadIdx.x & 3;
+  const auto rp = gmem(rp_);
+  const auto col = gmem(col_);
+  const auto val = gmem(val_);
+  for (int32_t q = (int32_t)(threadIdx.x >> 2); q < n; q += kTailRows) {
+    // addition runs as subtraction of the negated products (the same IEEE operation)
+    const T acc = quad_row_sub<T, tail_chunks<T>()>((MODE == 0) ? b[q] : (T)0, rp[q], rp[q + 1], col, val, lane,
+                                               [&](int32_t c, T a) {
+                                                 const T xv = x[c < 0 ? 0 : c];
+                                                 const T pr = (c >= 0) ? a * xv : (T)0;
+                                                 return MODE == 0 ? pr : -pr;
+                                               });
+    if (lane == 3) {
       if (MODE == 2) {
         const T yn = y[q] + acc;
         y[q] = yn;
@@ -95,10 +86,13 @@ __device__ void tail_rows(int32_t n, const int32_t* rp, const int32_t* col, cons
 }
 
 template <typename T>
-__device__ void tail_sweep(const TailLevel<T>& L, int& cur, bool zero) {
-  T* S[2] = {L.s0, L.s1};
+__device__ __forceinline__ void tail_sweep(const TailLevel<T>& L, T* V, int& cur, bool zero) {
+  // snapshots selected by value (an indexed pointer array would live in scratch)
+  T* s_in = cur ? V + L.off_s1 : V + L.off_s0;
+  T* s_out = cur ? V + L.off_s0 : V + L.off_s1;
+  const auto coff = gmem(L.coff);
   for (int c = 0; c < L.ncol; ++c) {
-    tail_colour<T>(L, L.coff[c], L.coff[c + 1], S[cur], S[cur ^ 1], zero);
+    tail_colour<T>(L, V, coff[c], coff[c + 1], s_in, s_out, zero);
     __syncthreads();
   }
   cur ^= 1;
@@ -109,7 +103,14 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_vcycle(const TailLevel<T>
                                                                int pre, int post, int32_t n_coarse,
                                                                const double* __restrict__ lu,
                                                                const int32_t* __restrict__ rperm) {
-  extern __shared__ double xs[];
+  extern __shared__ double lds[];
+  double* xs = lds;                                          // coarsest-solve staging
+  T* V = reinterpret_cast<T*>(lds + tail_lds_doubles(n_coarse));  // level vectors
+  {
+    const TailLevel<T>& F = levels[0];
+    for (int32_t i = threadIdx.x; i < F.n; i += kTailThreads) V[F.off_b + i] = gmem(F.gb)[i];
+    __syncthreads();
+  }
   // Snapshot bookkeeping: every sweep reads S[cur] and writes S[cur ^ 1], so
   // after the pre-sweeps S[pre & 1] equals x on every level.
   // down: smoothing from zero, residual, restriction
@@ -117,30 +118,32 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_vcycle(const TailLevel<T>
     const TailLevel<T>& L = levels[l];
     int cur = 0;
     if (pre == 0) {
-      for (int32_t q = threadIdx.x; q < L.n; q += kTailThreads) L.x[q] = (T)0;
+      for (int32_t q = threadIdx.x; q < L.n; q += kTailThreads) V[L.off_x + q] = (T)0;
       __syncthreads();
     }
-    for (int w = 0; w < pre; ++w) tail_sweep<T>(L, cur, w == 0);
-    tail_rows<T, 0>(L.n, L.a_rp, L.a_col, L.a_val, L.b, L.x, L.r, nullptr);
+    for (int w = 0; w < pre; ++w) tail_sweep<T>(L, V, cur, w == 0);
+    tail_rows<T, 0>(L.n, L.a_rp, L.a_col, L.a_val, V + L.off_b, V + L.off_x, V + L.off_r, nullptr);
     __syncthreads();
     const TailLevel<T>& C = levels[l + 1];
-    tail_rows<T, 1>(C.n, L.r_rp, L.r_col, L.r_val, nullptr, L.r, C.b, nullptr);
+    tail_rows<T, 1>(C.n, L.r_rp, L.r_col, L.r_val, nullptr, V + L.off_r, V + C.off_b, nullptr);
     __syncthreads();
   }
   // coarsest: P A = L U in FP64.  rperm composes the row swaps of the
   // factorisation, so (P b)_i = b[rperm[i]].
   {
     const TailLevel<T>& L = levels[nlev - 1];
+    const T* b = V + L.off_b;
+    T* x = V + L.off_x;
     const int n = n_coarse;
     if (n <= kWave) {
       // one wavefront, one row per lane, factors staged in LDS; the lanes stay
       // in lockstep, so no barrier is needed between substitution steps
       double* luS = xs + kWave;
-      for (int i = threadIdx.x; i < n * n; i += kTailThreads) luS[i] = lu[i];
+      for (int i = threadIdx.x; i < n * n; i += kTailThreads) luS[i] = gmem(lu)[i];
       __syncthreads();
       if (threadIdx.x < kWave) {
         const int r = threadIdx.x;
-        double xr = r < n ? (double)L.b[rperm[r]] : 0.0;
+        double xr = r < n ? (double)b[gmem(rperm)[r]] : 0.0;
         for (int k = 0; k < n; ++k) {
           const double xk = __shfl(xr, k, kWave);
           if (r > k && r < n) xr = xr - luS[r * n + k] * xk;
@@ -150,11 +153,11 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_vcycle(const TailLevel<T>
           const double xk = __shfl(xr, k, kWave);
           if (r < k) xr = xr - luS[r * n + k] * xk;
         }
-        if (r < n) L.x[r] = (T)xr;
+        if (r < n) x[r] = (T)xr;
       }
       __syncthreads();
     } else {
-      for (int i = threadIdx.x; i < n; i += kTailThreads) xs[i] = (double)L.b[rperm[i]];
+      for (int i = threadIdx.x; i < n; i += kTailThreads) xs[i] = (double)b[gmem(rperm)[i]];
       __syncthreads();
       for (int k = 0; k < n; ++k) {
         const double xk = xs[k];
@@ -168,7 +171,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_vcycle(const TailLevel<T>
         for (int r = threadIdx.x; r < k; r += kTailThreads) xs[r] = xs[r] - lu[(int64_t)r * n + k] * xk;
         __syncthreads();
       }
-      for (int i = threadIdx.x; i < n; i += kTailThreads) L.x[i] = (T)xs[i];
+      for (int i = threadIdx.x; i < n; i += kTailThreads) x[i] = (T)xs[i];
       __syncthreads();
     }
   }
@@ -176,26 +179,35 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_vcycle(const TailLevel<T>
   for (int l = nlev - 2; l >= 0; --l) {
     const TailLevel<T>& L = levels[l];
     const TailLevel<T>& C = levels[l + 1];
-    T* S[2] = {L.s0, L.s1};
     int cur = pre & 1;
-    tail_rows<T, 2>(L.n, L.p_rp, L.p_col, L.p_val, nullptr, C.x, L.x, S[cur]);
+    tail_rows<T, 2>(L.n, L.p_rp, L.p_col, L.p_val, nullptr, V + C.off_x, V + L.off_x,
+                    cur ? V + L.off_s1 : V + L.off_s0);
     __syncthreads();
-    for (int w = 0; w < post; ++w) tail_sweep<T>(L, cur, false);
+    for (int w = 0; w < post; ++w) tail_sweep<T>(L, V, cur, false);
   }
+  {
+    const TailLevel<T>& F = levels[0];
+    for (int32_t i = threadIdx.x; i < F.n; i += kTailThreads) F.gx[i] = V[F.off_x + i];
+  }
+}
+
+size_t tail_lds_limit() {
+  int dev = 0, bytes = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+  return static_cast<size_t>(bytes);
 }
 
 template <typename T>
 void launch_tail_vcycle(const TailLevel<T>* levels, int nlev, int pre, int post, int32_t n_coarse, const double* lu,
-                        const int32_t* rperm, hipStream_t s) {
-  const size_t lds = n_coarse <= kWave ? (kWave + (size_t)n_coarse * n_coarse) * sizeof(double)
-                                       : (size_t)n_coarse * sizeof(double);
-  hipLaunchKernelGGL((k_tail_vcycle<T>), dim3(1), dim3(kTailThreads), lds, s, levels, nlev, pre, post, n_coarse, lu,
-                     rperm);
+                        const int32_t* rperm, size_t lds_bytes, hipStream_t s) {
+  hipLaunchKernelGGL((k_tail_vcycle<T>), dim3(1), dim3(kTailThreads), lds_bytes, s, levels, nlev, pre, post, n_coarse,
+                     lu, rperm);
   CPR_LAUNCH_CHECK();
 }
 template void launch_tail_vcycle<double>(const TailLevel<double>*, int, int, int, int32_t, const double*,
-                                         const int32_t*, hipStream_t);
+                                         const int32_t*, size_t, hipStream_t);
 template void launch_tail_vcycle<float>(const TailLevel<float>*, int, int, int, int32_t, const double*,
-                                        const int32_t*, hipStream_t);
+                                        const int32_t*, size_t, hipStream_t);
 
 }  // namespace cpr

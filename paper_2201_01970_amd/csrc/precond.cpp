@@ -65,15 +65,43 @@ int32_t layout_for(int32_t policy, int32_t n, double avg) {
   return (n >= kSellRows && avg <= kSellAvg) ? 1 : 16;
 }
 
+// Requests a row keeps in flight: enough that nine rows (or slices) in ten
+// finish in one batch (each further batch costs two dependent memory round
+// trips), no more (the registers held per lane limit the waves in flight).
+// SELL: slots of a slice, 8/16/32; quad-vector CSR: chunks of 16 entries per
+// quad, 2/4/8; 16-lane CSR: chunks of 16 entries, 4/8/16.
+int32_t p90(std::vector<int32_t> v) {
+  if (v.empty()) return 0;
+  const size_t k = static_cast<size_t>(0.9 * (v.size() - 1));
+  std::nth_element(v.begin(), v.begin() + k, v.end());
+  return v[k];
+}
+
+int32_t csr_depth(const HostCsr& A, int32_t group) {
+  std::vector<int32_t> len(A.n_rows);
+  for (int32_t i = 0; i < A.n_rows; ++i) len[i] = A.ptr[i + 1] - A.ptr[i];
+  const int32_t w = p90(std::move(len));
+  if (group == 4) return w <= 32 ? 2 : (w <= 64 ? 4 : 8);
+  return w <= 64 ? 4 : (w <= 128 ? 8 : 16);
+}
+
+int32_t sell_depth(const std::vector<int32_t>& slice_ptr) {
+  std::vector<int32_t> width(slice_ptr.size() > 0 ? slice_ptr.size() - 1 : 0);
+  for (size_t s = 0; s < width.size(); ++s) width[s] = slice_ptr[s + 1] - slice_ptr[s];
+  const int32_t w = p90(std::move(width));
+  return w <= 8 ? 8 : (w <= 16 ? 16 : 32);
+}
+
 template <typename T>
 struct DevMat {
   int32_t n_rows = 0;
   int32_t group = 1;
+  int32_t depth = 8;
   int64_t stored = 0;  // stored entries including SELL padding
   int32_t* ptr = nullptr;
   int32_t* col = nullptr;
   T* val = nullptr;
-  MatView<T> view() const { return MatView<T>{n_rows, group, ptr, col, val}; }
+  MatView<T> view() const { return MatView<T>{n_rows, group, depth, ptr, col, val}; }
 };
 
 template <typename T>
@@ -84,10 +112,11 @@ DevMat<T> upload_mat(Arena& ar, const HostCsr& A, const std::vector<int32_t>& or
   D.n_rows = n;
   const double avg = n > 0 ? static_cast<double>(A.nnz()) / n : 0.0;
   int32_t layout = layout_for(policy, n, avg);
-  if (force_csr) layout = 16;
+  if (force_csr) layout = 4;
   if (layout == 1) {
     const SellHost S = build_sell(A, order, colmap);
     D.group = 1;
+    D.depth = sell_depth(S.slice_ptr);
     D.stored = static_cast<int64_t>(S.col.size());
     D.ptr = ar.upload(S.slice_ptr);
     D.col = ar.upload(S.col);
@@ -95,19 +124,27 @@ DevMat<T> upload_mat(Arena& ar, const HostCsr& A, const std::vector<int32_t>& or
     D.val = ar.upload(v);
     return D;
   }
+  // Quad-vector CSR pads every row to a multiple of four entries (column -1,
+  // value 0), so each row starts on a 16-byte boundary of the column array.
+  const int32_t pad = layout == 4 ? 4 : 1;
   std::vector<int32_t> rp(n + 1, 0), col;
   std::vector<T> val;
-  col.reserve(A.nnz());
-  val.reserve(A.nnz());
+  col.reserve(A.nnz() + (pad - 1) * static_cast<size_t>(n));
+  val.reserve(A.nnz() + (pad - 1) * static_cast<size_t>(n));
   for (int32_t p = 0; p < n; ++p) {
     const int32_t i = order[p];
     for (int32_t q = A.ptr[i]; q < A.ptr[i + 1]; ++q) {
       col.push_back(colmap.empty() ? A.col[q] : colmap[A.col[q]]);
       val.push_back(static_cast<T>(A.val[q]));
     }
+    while (col.size() % pad != 0) {
+      col.push_back(kPadCol);
+      val.push_back(static_cast<T>(0));
+    }
     rp[p + 1] = static_cast<int32_t>(col.size());
   }
   D.group = layout;
+  D.depth = csr_depth(A, layout);
   D.stored = static_cast<int64_t>(col.size());
   D.ptr = ar.upload(rp);
   D.col = ar.upload(col);
@@ -147,10 +184,23 @@ class Precond final : public PrecondBase {
     const double sv = sizeof(T);
     std::vector<std::vector<int32_t>> inv(nl);
     for (int l = 0; l < nl; ++l) inv[l] = inverse_perm(hl[l].perm);
-    // first level of the one-workgroup tail: every level from it down is small
+    // First level of the one-workgroup tail: every level from it down has at
+    // most tail_nnz stored entries and all their vectors fit the LDS of one
+    // workgroup (five per level, two on the coarsest, after the FP64 staging
+    // of the coarsest solve).
+    const int32_t n_last = hl[nl - 1].A.n_rows;
+    const size_t lds_limit = tail_lds_limit();
+    auto lds_for = [&](int first) {
+      size_t v = 2 * static_cast<size_t>(n_last);
+      for (int l = first; l + 1 < nl; ++l) v += 5 * static_cast<size_t>(hl[l].A.n_rows);
+      return static_cast<size_t>(tail_lds_doubles(n_last)) * sizeof(double) + v * sizeof(T);
+    };
     tail_ = nl - 1;
     if (prm.tail_nnz > 0)
-      while (tail_ > 0 && hl[tail_ - 1].A.nnz() <= prm.tail_nnz) --tail_;
+      while (tail_ > 0 && hl[tail_ - 1].A.nnz() <= prm.tail_nnz && lds_for(tail_ - 1) <= lds_limit) --tail_;
+    if (lds_for(tail_) > lds_limit)
+      throw Error(CPR_ERR_INVALID_ARG, "the coarsest level does not fit one workgroup's LDS (lower coarse_max)");
+    tail_lds_ = lds_for(tail_);
     for (int l = 0; l < nl; ++l) {
       Level& L = lv_[l];
       const HostLevel& H = hl[l];
@@ -198,15 +248,25 @@ class Precond final : public PrecondBase {
     std::iota(rperm.begin(), rperm.end(), 0);
     for (size_t k = 0; k < piv.size(); ++k) std::swap(rperm[k], rperm[piv[k]]);
     piv_ = ar_.upload(rperm);
-    // device descriptors of the tail levels
+    // device descriptors of the tail levels, with their LDS vector offsets
     std::vector<TailLevel<T>> td(nl - tail_);
+    int32_t off = 0;
     for (int l = tail_; l < nl; ++l) {
       Level& L = lv_[l];
       TailLevel<T>& d = td[l - tail_];
       d.n = L.n;
-      d.x = L.x;
-      d.b = L.b;
+      d.off_x = off;
+      d.off_b = off + L.n;
+      off += 2 * L.n;
+      if (l == tail_) {
+        d.gx = L.x;
+        d.gb = L.b;
+      }
       if (l + 1 < nl) {
+        d.off_r = off;
+        d.off_s0 = off + L.n;
+        d.off_s1 = off + 2 * L.n;
+        off += 3 * L.n;
         L.coff_d = ar_.upload(L.coff);
         d.ncol = static_cast<int32_t>(L.coff.size()) - 1;
         d.coff = L.coff_d;
@@ -220,9 +280,6 @@ class Precond final : public PrecondBase {
         d.r_rp = L.R.ptr;
         d.r_col = L.R.col;
         d.r_val = L.R.val;
-        d.r = L.r;
-        d.s0 = L.s0;
-        d.s1 = L.s1;
       }
     }
     tail_dev_ = ar_.upload(td);
@@ -347,7 +404,7 @@ class Precond final : public PrecondBase {
     const int nl = static_cast<int>(lv_.size());
     if (l == tail_) {
       if (timer) timer->begin(CPR_KSTAT_TAIL, s);
-      launch_tail_vcycle<T>(tail_dev_, nl - tail_, pre_, post_, nL_, lu_, piv_, s);
+      launch_tail_vcycle<T>(tail_dev_, nl - tail_, pre_, post_, nL_, lu_, piv_, tail_lds_, s);
       if (timer) timer->end(CPR_KSTAT_TAIL, s, tail_bytes_);
       return;
     }
@@ -380,6 +437,7 @@ class Precond final : public PrecondBase {
   Arena ar_;
   std::vector<Level> lv_;
   int tail_ = 0;
+  size_t tail_lds_ = 0;  // dynamic LDS bytes of the tail kernel
   TailLevel<T>* tail_dev_ = nullptr;
   double tail_bytes_ = 0.0;
   int pre_, post_;
