@@ -153,6 +153,9 @@ def serve_bench(args):
                 req, ticket, keep = item
                 x, info = srv.wait(ticket)
                 results[req] = (info, time.perf_counter() - t0)
+                if len(results) % 32 == 0:
+                    print(f"[serve] {len(results)}/{len(sub_descs)} done at {time.perf_counter() - t0:.1f}s",
+                          file=sys.stderr, flush=True)
 
         done_submitting = threading.Event()
         th = threading.Thread(target=waiter)
@@ -209,31 +212,40 @@ KERNEL_NAMES = {
     3: "stage2_block_gs", 4: "pgs_scm_colour_sweep_coarse", 5: "residual_restrict_prolong_coarse",
     6: "tail_vcycle_one_workgroup",
 }
+# Sources each timed kernel class is built from (a change to any of them
+# invalidates the committed counter measurement of that class).
+_COMMON_SRC = ["kernels_common.hpp", "device.hpp"]
 KERNEL_SOURCES = {
-    "bsr_spmv_fp64": "kernels_fine.hip", "stage2_block_gs": "kernels_fine.hip",
-    "pgs_scm_colour_sweep_level0": "kernels_amg.hip", "pgs_scm_colour_sweep_coarse": "kernels_amg.hip",
-    "residual_restrict_prolong_level0": "kernels_amg.hip", "residual_restrict_prolong_coarse": "kernels_amg.hip",
-    "tail_vcycle_one_workgroup": "kernels_tail.hip",
+    "bsr_spmv_fp64": ["kernels_fine.hip"] + _COMMON_SRC,
+    "stage2_block_gs": ["kernels_fine.hip"] + _COMMON_SRC,
+    "pgs_scm_colour_sweep_level0": ["kernels_amg.hip"] + _COMMON_SRC,
+    "pgs_scm_colour_sweep_coarse": ["kernels_amg.hip"] + _COMMON_SRC,
+    "residual_restrict_prolong_level0": ["kernels_amg.hip"] + _COMMON_SRC,
+    "residual_restrict_prolong_coarse": ["kernels_amg.hip"] + _COMMON_SRC,
+    "tail_vcycle_one_workgroup": ["kernels_tail.hip"] + _COMMON_SRC,
 }
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_spe10_3.28M_fp32.json")
 
 
-def _source_hash(fname):
+def _source_hash(fnames):
     import hashlib
 
-    path = os.path.join(ROOT, "paper_2201_01970_amd", "csrc", fname)
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for fname in fnames:
+        with open(os.path.join(ROOT, "paper_2201_01970_amd", "csrc", fname), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def _measured_traffic(kernel):
-    """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current source of the kernel (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
-    if not os.path.exists(path):
+def _measured_traffic(kernel, workload):
+    """HBM bytes per launch of a kernel class from the committed counter
+    summary, if it was taken on this workload and on the current sources of
+    the class (else None)."""
+    if workload != "spe10" or not os.path.exists(TRAFFIC_FILE):
         return None
-    with open(path) as f:
+    with open(TRAFFIC_FILE) as f:
         data = json.load(f)
-    rec = data.get(kernel)
+    rec = data.get("classes", {}).get(kernel)
     if not rec or rec.get("source_sha256_16") != _source_hash(KERNEL_SOURCES[kernel]):
         return None
     return rec.get("hbm_bytes_per_launch")
@@ -452,7 +464,7 @@ def main():
     if dom:
         d = kernels[dom]
         roof = {"bound": "hbm", "kernel": dom, "achieved": d["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": d["achieved_GBs"] / HBM_PEAK_GBS, "traffic": _measured_traffic(dom)}
+                "frac": d["achieved_GBs"] / HBM_PEAK_GBS, "traffic": _measured_traffic(dom, args.workload)}
 
     med32 = statistics.median(r32["times"])
     out = {

@@ -170,7 +170,9 @@ cpr_status cpr_setup(const cpr_bsr* A, const cpr_params* p, void* hip_stream, cp
     copy_in(h->h_row_ptr.data(), A->row_ptr, (h->n_b + 1) * sizeof(int32_t), A->location);
     copy_in(h->h_col.data(), A->col_idx, h->nnz_b * sizeof(int32_t), A->location);
     validate_pattern(h->n_b, h->nnz_b, h->h_row_ptr, h->h_col);
-    h->phash = pattern_hash(h->n_b, h->nnz_b, h->h_row_ptr.data(), h->h_col.data());
+    h->d_rp_pat = h->fine.upload(h->h_row_ptr);
+    h->d_col_pat = h->fine.upload(h->h_col);
+    h->d_flag = h->fine.alloc<int32_t>(1);
     h->h_vals.resize(static_cast<size_t>(h->nnz_b) * 9);
     copy_in(h->h_vals.data(), A->values, h->h_vals.size() * sizeof(double), A->location);
     h->h_vals_valid = true;
@@ -195,11 +197,23 @@ cpr_status cpr_update_values(cpr_handle* h, const cpr_bsr* A) {
     check_bsr(A);
     if (A->n_block_rows != h->n_b || A->nnz_blocks != h->nnz_b)
       throw Error(CPR_ERR_SIZE_MISMATCH, "matrix size differs from the handle's (a new SETUP is required)");
-    std::vector<int32_t> rp(h->n_b + 1), col(h->nnz_b);
-    copy_in(rp.data(), A->row_ptr, rp.size() * sizeof(int32_t), A->location);
-    copy_in(col.data(), A->col_idx, col.size() * sizeof(int32_t), A->location);
-    if (pattern_hash(h->n_b, h->nnz_b, rp.data(), col.data()) != h->phash)
-      throw Error(CPR_ERR_PATTERN_MISMATCH, "sparsity pattern differs from the handle's");
+    // exact comparison with the SETUP pattern, where the new arrays live
+    bool same = true;
+    if (A->location == CPR_MEM_DEVICE) {
+      // synchronising calls stay exclusive with step-graph captures in other threads
+      std::lock_guard<std::mutex> lk(device_api_mutex());
+      int32_t diff = 0;
+      HIPCHK(hipMemsetAsync(h->d_flag, 0, sizeof(int32_t), h->stream));
+      launch_int_diff(h->n_b + 1, A->row_ptr, h->d_rp_pat, h->d_flag, h->stream);
+      launch_int_diff(h->nnz_b, A->col_idx, h->d_col_pat, h->d_flag, h->stream);
+      HIPCHK(hipMemcpyAsync(&diff, h->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+      same = diff == 0;
+    } else {
+      same = std::equal(A->row_ptr, A->row_ptr + h->n_b + 1, h->h_row_ptr.begin()) &&
+             std::equal(A->col_idx, A->col_idx + h->nnz_b, h->h_col.begin());
+    }
+    if (!same) throw Error(CPR_ERR_PATTERN_MISMATCH, "sparsity pattern differs from the handle's");
     const size_t bytes = static_cast<size_t>(h->nnz_b) * 9 * sizeof(double);
     if (A->location == CPR_MEM_DEVICE) {
       HIPCHK(hipMemcpyAsync(h->d_vals_in, A->values, bytes, hipMemcpyDeviceToDevice, h->stream));

@@ -156,6 +156,8 @@ void launch_fill(int64_t n, T value, T* dst, hipStream_t s);
 template <typename TS, typename TD>
 void launch_copy_cast(int64_t n, const TS* src, TD* dst, hipStream_t s);
 void launch_copy_bytes(int64_t n_bytes, const void* src, void* dst, hipStream_t s);
+// *flag = 1 if the int arrays a and b (device, n entries) differ anywhere; *flag is not cleared
+void launch_int_diff(int64_t n, const int32_t* a, const int32_t* b, int32_t* flag, hipStream_t s);
 
 // ---- Krylov kernels (FP64) ----
 int krylov_grid(int64_t n);

@@ -474,19 +474,4 @@ bool dense_lu(int32_t n, std::vector<double>& a, std::vector<int32_t>& piv) {
   return true;
 }
 
-uint64_t pattern_hash(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col) {
-  uint64_t h = 1469598103934665603ull;
-  auto mix = [&h](uint32_t v) {
-    for (int b = 0; b < 4; ++b) {
-      h ^= (v >> (8 * b)) & 0xffu;
-      h *= 1099511628211ull;
-    }
-  };
-  mix(static_cast<uint32_t>(n));
-  mix(static_cast<uint32_t>(nnz));
-  for (int32_t i = 0; i <= n; ++i) mix(static_cast<uint32_t>(row_ptr[i]));
-  for (int32_t p = 0; p < nnz; ++p) mix(static_cast<uint32_t>(col[p]));
-  return h;
-}
-
 }  // namespace cpr

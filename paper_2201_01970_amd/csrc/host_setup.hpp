@@ -73,7 +73,4 @@ bool dense_lu(int32_t n, std::vector<double>& a, std::vector<int32_t>& piv);
 // Host threads used by the row-parallel SETUP steps (at most 16).
 int setup_threads();
 
-// 64-bit FNV-1a hash of a BSR pattern (sizes, row_ptr, col).
-uint64_t pattern_hash(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col);
-
 }  // namespace cpr

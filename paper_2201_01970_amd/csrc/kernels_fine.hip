@@ -402,6 +402,19 @@ template void launch_copy_cast<double, float>(int64_t, const double*, float*, hi
 template void launch_copy_cast<float, double>(int64_t, const float*, double*, hipStream_t);
 template void launch_copy_cast<float, float>(int64_t, const float*, float*, hipStream_t);
 
+// flag = 1 if a[i] != b[i] for some i < n (every writer stores the same value).
+__global__ __launch_bounds__(kBlock) void k_int_diff(int64_t n, const int32_t* __restrict__ a,
+                                                     const int32_t* __restrict__ b, int32_t* __restrict__ flag) {
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += (int64_t)gridDim.x * kBlock)
+    if (a[k] != b[k]) *flag = 1;
+}
+void launch_int_diff(int64_t n, const int32_t* a, const int32_t* b, int32_t* flag, hipStream_t s) {
+  if (n <= 0) return;
+  const int grid = (int)std::min<int64_t>(div_up(n, kBlock), 4096);
+  hipLaunchKernelGGL(k_int_diff, dim3(grid), dim3(kBlock), 0, s, n, a, b, flag);
+  CPR_LAUNCH_CHECK();
+}
+
 // Plain streaming copy in 16-byte words (tail in bytes); used to calibrate
 // hardware traffic counters against a kernel of known size.
 __global__ __launch_bounds__(kBlock) void k_copy_bytes(int64_t n16, const uint4* __restrict__ src,

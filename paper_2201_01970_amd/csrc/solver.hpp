@@ -153,7 +153,8 @@ struct cpr_handle {
   hipStream_t stream = nullptr;  // caller's stream (NULL = default stream)
   int device = 0;
   int32_t n_b = 0, nnz_b = 0;
-  uint64_t phash = 0;
+  int32_t *d_rp_pat = nullptr, *d_col_pat = nullptr;  // the input pattern on the device
+  int32_t* d_flag = nullptr;                           // pattern comparison result
   std::vector<int32_t> h_row_ptr, h_col;
   std::vector<double> h_vals;
   bool h_vals_valid = false;
