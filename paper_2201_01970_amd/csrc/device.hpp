@@ -36,8 +36,9 @@ struct SellView {
 template <typename T>
 struct MatView {
   int32_t n_rows = 0;
-  int32_t group = 1;   // 1: SELL-64, one lane per row; 16/32/64: CSR, lanes per row
+  int32_t group = 1;   // 1: SELL-64, one lane per row; 4: quad-vector CSR; 16/32/64: CSR, lanes per row
   int32_t depth = 8;   // requests in flight per row: SELL slots (8, 16, 32) or CSR chunks of `group` (4, 8, 16)
+  int32_t width = 0;   // SELL: width of every slice when all are equal (ptr unused), else 0
   const int32_t* ptr = nullptr;
   const int32_t* col = nullptr;
   const T* val = nullptr;

@@ -193,24 +193,62 @@ int32_t vertices_grouping(const Pattern& S, std::vector<int32_t>& colour) {
 
 // ------------------------------------------------------------ RS split
 namespace {
-struct LamKey {
-  int64_t lam;
-  int32_t i;
-};
-struct LamLess {
-  bool operator()(const LamKey& a, const LamKey& b) const {
-    if (a.lam != b.lam) return a.lam < b.lam;
-    return a.i > b.i;
+// A set of indices in [0, n) with insert, erase and smallest-member queries in
+// O(log_64 n): a 64-ary tree of occupancy words (bit b of word w on a level
+// says whether word 64w + b of the level below has any bit set).
+class IndexSet {
+ public:
+  explicit IndexSet(int32_t n) {
+    int64_t words = (static_cast<int64_t>(n) + 63) / 64;
+    do {
+      lv_.emplace_back(static_cast<size_t>(std::max<int64_t>(words, 1)), 0ull);
+      words = (words + 63) / 64;
+    } while (lv_.back().size() > 1);
   }
+  void insert(int32_t i) {
+    uint64_t idx = static_cast<uint64_t>(i);
+    for (auto& w : lv_) {
+      const bool was_empty = w[idx >> 6] == 0;
+      w[idx >> 6] |= 1ull << (idx & 63);
+      if (!was_empty) break;
+      idx >>= 6;
+    }
+  }
+  void erase(int32_t i) {
+    uint64_t idx = static_cast<uint64_t>(i);
+    for (auto& w : lv_) {
+      w[idx >> 6] &= ~(1ull << (idx & 63));
+      if (w[idx >> 6] != 0) break;
+      idx >>= 6;
+    }
+  }
+  bool empty() const { return lv_.back()[0] == 0; }
+  int32_t first() const {  // smallest member; the set must not be empty
+    uint64_t idx = 0;
+    for (size_t l = lv_.size(); l-- > 0;) idx = (idx << 6) | static_cast<uint64_t>(__builtin_ctzll(lv_[l][idx]));
+    return static_cast<int32_t>(idx);
+  }
+
+ private:
+  std::vector<std::vector<uint64_t>> lv_;  // lv_[0]: one bit per index
 };
 }  // namespace
 
+// First pass: repeatedly take the undecided point of largest lambda (ties to
+// the smallest index).  Points are kept in one IndexSet per lambda value;
+// lambda_i never exceeds 2|S^T_i| (it grows by one for each strong dependent
+// that turns F), which bounds the number of sets.
 void rs_split(const Pattern& S, const Pattern& ST, std::vector<int8_t>& cf) {
   constexpr int8_t U = 0, C = 1, F = 2;
   const int32_t n = S.n;
   cf.assign(n, U);
-  std::vector<int64_t> lam(n, 0);
-  std::vector<LamKey> init;
+  std::vector<int32_t> lam(n, 0);
+  int32_t max_st = 0;
+  for (int32_t i = 0; i < n; ++i) max_st = std::max(max_st, ST.ptr[i + 1] - ST.ptr[i]);
+  std::vector<IndexSet> bucket;
+  bucket.reserve(2 * static_cast<size_t>(max_st) + 1);
+  for (int32_t v = 0; v <= 2 * max_st; ++v) bucket.emplace_back(n);
+  int32_t top = 0;
   for (int32_t i = 0; i < n; ++i) {
     const bool no_s = S.ptr[i + 1] == S.ptr[i];
     const bool no_st = ST.ptr[i + 1] == ST.ptr[i];
@@ -218,34 +256,37 @@ void rs_split(const Pattern& S, const Pattern& ST, std::vector<int8_t>& cf) {
       cf[i] = F;
     } else {
       lam[i] = ST.ptr[i + 1] - ST.ptr[i];
-      init.push_back({lam[i], i});
+      bucket[lam[i]].insert(i);
+      top = std::max(top, lam[i]);
     }
   }
-  std::priority_queue<LamKey, std::vector<LamKey>, LamLess> heap(LamLess(), std::move(init));
-  while (!heap.empty()) {
-    LamKey top = heap.top();
-    heap.pop();
-    const int32_t i = top.i;
-    if (cf[i] != U || top.lam != lam[i]) continue;  // stale entry
-    if (lam[i] == 0) break;
+  while (true) {
+    while (top > 0 && bucket[top].empty()) --top;
+    if (top == 0) break;  // every undecided point left has lambda = 0
+    const int32_t i = bucket[top].first();
+    bucket[top].erase(i);
     cf[i] = C;
     for (int32_t p = ST.ptr[i]; p < ST.ptr[i + 1]; ++p) {
       const int32_t j = ST.col[p];
       if (cf[j] != U) continue;
       cf[j] = F;
+      bucket[lam[j]].erase(j);
       for (int32_t q = S.ptr[j]; q < S.ptr[j + 1]; ++q) {
         const int32_t k = S.col[q];
         if (cf[k] == U) {
+          bucket[lam[k]].erase(k);
           lam[k] += 1;
-          heap.push({lam[k], k});
+          bucket[lam[k]].insert(k);
+          top = std::max(top, lam[k]);
         }
       }
     }
     for (int32_t p = S.ptr[i]; p < S.ptr[i + 1]; ++p) {
       const int32_t j = S.col[p];
       if (cf[j] == U) {
+        bucket[lam[j]].erase(j);
         lam[j] -= 1;
-        heap.push({lam[j], j});
+        bucket[lam[j]].insert(j);
       }
     }
   }

@@ -28,11 +28,14 @@ namespace cpr {
 // with the loads of U consecutive slots issued together (U is chosen per
 // matrix from its slice widths, so most rows take one batch: every further
 // batch costs two dependent memory round trips).
+// A matrix whose slices all have the same width (width > 0) needs no slice
+// pointer: the slot range is computed, which saves a dependent load.
 template <typename T, int U, typename F>
-__device__ __forceinline__ void sell_row(int32_t q, const int32_t* __restrict__ slice_ptr,
+__device__ __forceinline__ void sell_row(int32_t q, int32_t width, const int32_t* __restrict__ slice_ptr,
                                          const int32_t* __restrict__ col, const T* __restrict__ val, F&& f) {
   const int32_t slice = q >> 6, lane = q & 63;
-  const int32_t t0 = slice_ptr[slice], t1 = slice_ptr[slice + 1];
+  const int32_t t0 = width > 0 ? slice * width : slice_ptr[slice];
+  const int32_t t1 = width > 0 ? t0 + width : slice_ptr[slice + 1];
   for (int32_t t = t0; t < t1; t += U) {
     int32_t c[U];
     T a[U];
@@ -105,7 +108,8 @@ __device__ __forceinline__ T gs_prod(int32_t q, int32_t c, T a, int32_t lo, int3
 }
 
 template <typename T, int U, bool ZERO>
-__global__ __launch_bounds__(kBlock) void k_gs_sell(int32_t lo, int32_t hi, const int32_t* __restrict__ slice_ptr,
+__global__ __launch_bounds__(kBlock) void k_gs_sell(int32_t lo, int32_t hi, int32_t width,
+                                                    const int32_t* __restrict__ slice_ptr,
                                                     const int32_t* __restrict__ col, const T* __restrict__ val,
                                                     const T* __restrict__ diag, const T* __restrict__ b,
                                                     T* __restrict__ x, const T* __restrict__ s_in,
@@ -114,7 +118,8 @@ __global__ __launch_bounds__(kBlock) void k_gs_sell(int32_t lo, int32_t hi, cons
   const int32_t q = base + xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (q < lo || q >= hi) return;
   T s = b[q];
-  sell_row<T, U>(q, slice_ptr, col, val, [&](int32_t c, T a) { s = s - gs_prod<T, ZERO>(q, c, a, lo, hi, x, s_in); });
+  sell_row<T, U>(q, width, slice_ptr, col, val,
+                 [&](int32_t c, T a) { s = s - gs_prod<T, ZERO>(q, c, a, lo, hi, x, s_in); });
   const T xn = s / diag[q];
   x[q] = xn;
   s_out[q] = xn;
@@ -213,11 +218,11 @@ void launch_gs_sell(const MatView<T>& A, const T* diag, int32_t lo, int32_t hi, 
   const int32_t base = lo & ~63;
   const int grid = div_up(hi - base, kBlock);
   if (zero_start)
-    hipLaunchKernelGGL((k_gs_sell<T, U, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag, b,
-                       x, s_in, s_out);
+    hipLaunchKernelGGL((k_gs_sell<T, U, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.width, A.ptr, A.col, A.val,
+                       diag, b, x, s_in, s_out);
   else
-    hipLaunchKernelGGL((k_gs_sell<T, U, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag, b,
-                       x, s_in, s_out);
+    hipLaunchKernelGGL((k_gs_sell<T, U, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.width, A.ptr, A.col,
+                       A.val, diag, b, x, s_in, s_out);
 }
 
 template <typename T>
@@ -274,14 +279,14 @@ __device__ __forceinline__ void finish_row(int32_t q, T acc, const T* __restrict
 }
 
 template <typename T, int U, int MODE>
-__global__ __launch_bounds__(kBlock) void k_rows_sell(int32_t n, const int32_t* __restrict__ slice_ptr,
+__global__ __launch_bounds__(kBlock) void k_rows_sell(int32_t n, int32_t width, const int32_t* __restrict__ slice_ptr,
                                                       const int32_t* __restrict__ col, const T* __restrict__ val,
                                                       const T* __restrict__ b, const T* __restrict__ x,
                                                       T* __restrict__ y, T* __restrict__ snap) {
   const int32_t q = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (q >= n) return;
   T acc = (MODE == 0) ? b[q] : (T)0;
-  sell_row<T, U>(q, slice_ptr, col, val, [&](int32_t c, T a) {
+  sell_row<T, U>(q, width, slice_ptr, col, val, [&](int32_t c, T a) {
     const T prod = (c >= 0) ? a * x[c] : (T)0;
     acc = (MODE == 0) ? (acc - prod) : (acc + prod);
   });
@@ -348,8 +353,8 @@ void launch_rows_grp(const MatView<T>& A, const T* b, const T* x, T* y, T* snap,
 
 template <typename T, int U, int MODE>
 void launch_rows_sell(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, hipStream_t s) {
-  hipLaunchKernelGGL((k_rows_sell<T, U, MODE>), dim3(div_up(A.n_rows, kBlock)), dim3(kBlock), 0, s, A.n_rows, A.ptr,
-                     A.col, A.val, b, x, y, snap);
+  hipLaunchKernelGGL((k_rows_sell<T, U, MODE>), dim3(div_up(A.n_rows, kBlock)), dim3(kBlock), 0, s, A.n_rows, A.width,
+                     A.ptr, A.col, A.val, b, x, y, snap);
 }
 
 template <typename T, int MODE>

@@ -15,24 +15,38 @@ namespace {
 // through `colmap`; entries keep their stored order.
 struct SellHost {
   int32_t n_rows = 0;
+  int32_t uniform = 0;  // width of every slice when all are equal, else 0
   std::vector<int32_t> slice_ptr, col;
   std::vector<double> val;
 };
 
+// When padding every slice to the widest one costs at most 5% more slots, all
+// slices get that width (uniform = the width), which lets the kernels compute
+// a slice's slot range instead of loading it.
 SellHost build_sell(const HostCsr& A, const std::vector<int32_t>& order, const std::vector<int32_t>& colmap) {
   SellHost S;
   const int32_t n = static_cast<int32_t>(order.size());
   S.n_rows = n;
   const int32_t ns = (n + kWave - 1) / kWave;
-  S.slice_ptr.assign(ns + 1, 0);
+  std::vector<int32_t> width(ns, 0);
+  int32_t wmax = 0;
+  int64_t wsum = 0;
   for (int32_t s = 0; s < ns; ++s) {
     int32_t w = 0;
     for (int32_t p = s * kWave; p < std::min(n, (s + 1) * kWave); ++p) {
       const int32_t i = order[p];
       w = std::max(w, A.ptr[i + 1] - A.ptr[i]);
     }
-    S.slice_ptr[s + 1] = S.slice_ptr[s] + w;
+    width[s] = w;
+    wmax = std::max(wmax, w);
+    wsum += w;
   }
+  if (ns > 0 && wmax > 0 && static_cast<int64_t>(ns) * wmax * 20 <= wsum * 21) {
+    S.uniform = wmax;
+    std::fill(width.begin(), width.end(), wmax);
+  }
+  S.slice_ptr.assign(ns + 1, 0);
+  for (int32_t s = 0; s < ns; ++s) S.slice_ptr[s + 1] = S.slice_ptr[s] + width[s];
   const int64_t slots = S.slice_ptr[ns];
   S.col.assign(static_cast<size_t>(slots) * kWave, kPadCol);
   S.val.assign(static_cast<size_t>(slots) * kWave, 0.0);
@@ -97,11 +111,12 @@ struct DevMat {
   int32_t n_rows = 0;
   int32_t group = 1;
   int32_t depth = 8;
+  int32_t width = 0;
   int64_t stored = 0;  // stored entries including SELL padding
   int32_t* ptr = nullptr;
   int32_t* col = nullptr;
   T* val = nullptr;
-  MatView<T> view() const { return MatView<T>{n_rows, group, depth, ptr, col, val}; }
+  MatView<T> view() const { return MatView<T>{n_rows, group, depth, width, ptr, col, val}; }
 };
 
 template <typename T>
@@ -117,6 +132,7 @@ DevMat<T> upload_mat(Arena& ar, const HostCsr& A, const std::vector<int32_t>& or
     const SellHost S = build_sell(A, order, colmap);
     D.group = 1;
     D.depth = sell_depth(S.slice_ptr);
+    D.width = S.uniform;
     D.stored = static_cast<int64_t>(S.col.size());
     D.ptr = ar.upload(S.slice_ptr);
     D.col = ar.upload(S.col);

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <future>
 #include <numeric>
 
 namespace cpr {
@@ -107,6 +108,20 @@ void colour_order(int32_t n, const std::vector<int32_t>& ptr, const std::vector<
   for (int32_t c = 0; c < ncol; ++c) coff[c + 1] += coff[c];
 }
 
+// Greedy colouring of one level (Algorithm VerticesGrouping) and its device
+// row order; independent of the coarsening, so it runs on its own thread.
+struct Colouring {
+  std::vector<int32_t> colour, perm, coff;
+  int32_t n_colours = 0;
+};
+
+Colouring colour_level(const Pattern& S, const std::vector<int32_t>& ptr) {
+  Colouring c;
+  c.n_colours = vertices_grouping(S, c.colour);
+  colour_order(S.n, ptr, c.colour, c.n_colours, c.perm, c.coff);
+  return c;
+}
+
 }  // namespace
 
 }  // namespace cpr
@@ -116,10 +131,11 @@ using namespace cpr;
 // ------------------------------------------------------------------ SETUP
 // Pressure extraction (A_PP = Pi_P^T A Pi_P, the (0,0) entry of every stored
 // block), then per level: strength masks on the GPU, RS split, interpolation
-// and Galerkin product on the host, until the level is small enough; then the
+// and Galerkin product on the host, until the level is small enough; the
 // colouring of every smoothed level (Algorithm VerticesGrouping on eq.
-// (strong-matrix)), the coarsest LU, the stage-2 block colouring (theta = 0
-// on the block graph) and the device images.
+// (strong-matrix)) and the stage-2 block colouring (theta = 0 on the block
+// graph) run on threads of their own meanwhile; then the coarsest LU and the
+// device images.
 void cpr_handle::build_precond() {
   const double t0 = now_ms();
   if (!h_vals_valid) {
@@ -160,6 +176,28 @@ void cpr_handle::build_precond() {
     if (bad) throw Error(CPR_ERR_SINGULAR_BLOCK, "diagonal block of cell " + std::to_string(i) + " is singular");
   }
 
+  // The colourings depend only on each level's matrix and strength mask, not
+  // on the coarsening that follows, so they run on threads of their own while
+  // the levels are built: first the stage-2 block colouring (theta = 0 on the
+  // block graph: every stored nonzero off-diagonal block couples two cells).
+  auto block_task = std::async(std::launch::async, [this]() {
+    Pattern B;
+    B.n = n_b;
+    B.ptr.assign(n_b + 1, 0);
+    for (int32_t i = 0; i < n_b; ++i) {
+      for (int32_t k = h_row_ptr[i]; k < h_row_ptr[i + 1]; ++k) {
+        const int32_t j = h_col[k];
+        if (j == i) continue;
+        bool nz = false;
+        for (int e = 0; e < 9; ++e) nz = nz || h_vals[static_cast<size_t>(k) * 9 + e] != 0.0;
+        if (nz) B.col.push_back(j);
+      }
+      B.ptr[i + 1] = static_cast<int32_t>(B.col.size());
+    }
+    return colour_level(B, h_row_ptr);
+  });
+  std::vector<std::future<Colouring>> level_tasks;
+
   HostCsr A;
   A.n_rows = A.n_cols = n_b;
   A.ptr = h_row_ptr;
@@ -199,12 +237,17 @@ void cpr_handle::build_precond() {
     HIPCHK(hipMemcpyAsync(L.mask.data(), d_mask, L.A.nnz(), hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
 
+    // colouring of this level (eq. (strong-matrix) pattern) on its own thread
+    level_tasks.push_back(std::async(std::launch::async, [Sc = pattern_from_mask(L.A, L.mask, 2),
+                                                          ptr = L.A.ptr]() { return colour_level(Sc, ptr); }));
     const Pattern S = pattern_from_mask(L.A, L.mask, 1);
     const Pattern ST = transpose_pattern(S);
     rs_split(S, ST, L.cf);
     int32_t nc = 0;
     for (int8_t c : L.cf) nc += (c == 1);
     if (nc == 0 || static_cast<double>(nc) > 0.9 * n) {
+      // coarsening stalled: this level becomes the coarsest and is not smoothed
+      level_tasks.pop_back();
       L.cf.clear();
       hl.push_back(std::move(L));
       break;
@@ -222,9 +265,11 @@ void cpr_handle::build_precond() {
   for (int l = 0; l < nl; ++l) {
     HostLevel& L = hl[l];
     if (l + 1 < nl) {
-      const Pattern Sc = pattern_from_mask(L.A, L.mask, 2);
-      L.n_colours = vertices_grouping(Sc, L.colour);
-      colour_order(L.A.n_rows, L.A.ptr, L.colour, L.n_colours, L.perm, L.coff);
+      Colouring c = level_tasks[l].get();
+      L.colour = std::move(c.colour);
+      L.n_colours = c.n_colours;
+      L.perm = std::move(c.perm);
+      L.coff = std::move(c.coff);
     } else {
       L.perm.resize(L.A.n_rows);
       std::iota(L.perm.begin(), L.perm.end(), 0);
@@ -240,23 +285,11 @@ void cpr_handle::build_precond() {
   std::vector<int32_t> piv;
   if (!dense_lu(nc, lu, piv)) throw Error(CPR_ERR_SINGULAR_COARSE, "coarsest matrix is singular");
 
-  // stage-2 block colouring: theta = 0 on the block graph
-  Pattern B;
-  B.n = n_b;
-  B.ptr.assign(n_b + 1, 0);
-  for (int32_t i = 0; i < n_b; ++i) {
-    for (int32_t k = h_row_ptr[i]; k < h_row_ptr[i + 1]; ++k) {
-      const int32_t j = h_col[k];
-      if (j == i) continue;
-      bool nz = false;
-      for (int e = 0; e < 9; ++e) nz = nz || h_vals[static_cast<size_t>(k) * 9 + e] != 0.0;
-      if (nz) B.col.push_back(j);
-    }
-    B.ptr[i + 1] = static_cast<int32_t>(B.col.size());
-  }
-  n_block_colours = vertices_grouping(B, block_colour);
-  std::vector<int32_t> bperm, bcoff;
-  colour_order(n_b, h_row_ptr, block_colour, n_block_colours, bperm, bcoff);
+  // stage-2 block colouring (computed on its own thread since the start)
+  Colouring bc = block_task.get();
+  block_colour = std::move(bc.colour);
+  n_block_colours = bc.n_colours;
+  std::vector<int32_t> bperm = std::move(bc.perm), bcoff = std::move(bc.coff);
 
   pc = make_precond(prm.precond_fp32 != 0, prm, n_b, hl, lu, piv, bperm, bcoff, h_row_ptr, h_col, block_colour,
                     d_vals_in, stream);
