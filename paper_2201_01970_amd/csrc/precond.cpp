@@ -3,6 +3,7 @@
 // stage 2 = one forward multi-colour block Gauss-Seidel sweep, fused with the
 // prolongation Pi_P and the residual r = v - A z.
 #include <algorithm>
+#include <future>
 #include <numeric>
 
 #include "solver.hpp"
@@ -119,52 +120,68 @@ struct DevMat {
   MatView<T> view() const { return MatView<T>{n_rows, group, depth, width, ptr, col, val}; }
 };
 
+// Host image of a level matrix in the storage form its size and row lengths
+// call for (built on a worker thread, uploaded afterwards).
 template <typename T>
-DevMat<T> upload_mat(Arena& ar, const HostCsr& A, const std::vector<int32_t>& order,
-                     const std::vector<int32_t>& colmap, int32_t policy, bool force_csr = false) {
-  DevMat<T> D;
+struct HostMat {
+  int32_t n_rows = 0, group = 1, depth = 8, width = 0;
+  std::vector<int32_t> ptr, col;
+  std::vector<T> val;
+};
+
+template <typename T>
+HostMat<T> build_mat(const HostCsr& A, const std::vector<int32_t>& order, const std::vector<int32_t>& colmap,
+                     int32_t policy, bool force_csr = false) {
+  HostMat<T> M;
   const int32_t n = static_cast<int32_t>(order.size());
-  D.n_rows = n;
+  M.n_rows = n;
   const double avg = n > 0 ? static_cast<double>(A.nnz()) / n : 0.0;
   int32_t layout = layout_for(policy, n, avg);
   if (force_csr) layout = 4;
   if (layout == 1) {
-    const SellHost S = build_sell(A, order, colmap);
-    D.group = 1;
-    D.depth = sell_depth(S.slice_ptr);
-    D.width = S.uniform;
-    D.stored = static_cast<int64_t>(S.col.size());
-    D.ptr = ar.upload(S.slice_ptr);
-    D.col = ar.upload(S.col);
-    std::vector<T> v(S.val.begin(), S.val.end());
-    D.val = ar.upload(v);
-    return D;
+    SellHost S = build_sell(A, order, colmap);
+    M.group = 1;
+    M.depth = sell_depth(S.slice_ptr);
+    M.width = S.uniform;
+    M.ptr = std::move(S.slice_ptr);
+    M.col = std::move(S.col);
+    M.val.assign(S.val.begin(), S.val.end());
+    return M;
   }
   // Quad-vector CSR pads every row to a multiple of four entries (column -1,
   // value 0), so each row starts on a 16-byte boundary of the column array.
   const int32_t pad = layout == 4 ? 4 : 1;
-  std::vector<int32_t> rp(n + 1, 0), col;
-  std::vector<T> val;
-  col.reserve(A.nnz() + (pad - 1) * static_cast<size_t>(n));
-  val.reserve(A.nnz() + (pad - 1) * static_cast<size_t>(n));
+  M.ptr.assign(n + 1, 0);
+  M.col.reserve(A.nnz() + (pad - 1) * static_cast<size_t>(n));
+  M.val.reserve(A.nnz() + (pad - 1) * static_cast<size_t>(n));
   for (int32_t p = 0; p < n; ++p) {
     const int32_t i = order[p];
     for (int32_t q = A.ptr[i]; q < A.ptr[i + 1]; ++q) {
-      col.push_back(colmap.empty() ? A.col[q] : colmap[A.col[q]]);
-      val.push_back(static_cast<T>(A.val[q]));
+      M.col.push_back(colmap.empty() ? A.col[q] : colmap[A.col[q]]);
+      M.val.push_back(static_cast<T>(A.val[q]));
     }
-    while (col.size() % pad != 0) {
-      col.push_back(kPadCol);
-      val.push_back(static_cast<T>(0));
+    while (M.col.size() % pad != 0) {
+      M.col.push_back(kPadCol);
+      M.val.push_back(static_cast<T>(0));
     }
-    rp[p + 1] = static_cast<int32_t>(col.size());
+    M.ptr[p + 1] = static_cast<int32_t>(M.col.size());
   }
-  D.group = layout;
-  D.depth = csr_depth(A, layout);
-  D.stored = static_cast<int64_t>(col.size());
-  D.ptr = ar.upload(rp);
-  D.col = ar.upload(col);
-  D.val = ar.upload(val);
+  M.group = layout;
+  M.depth = csr_depth(A, layout);
+  return M;
+}
+
+template <typename T>
+DevMat<T> upload_mat(Arena& ar, const HostMat<T>& M) {
+  DevMat<T> D;
+  D.n_rows = M.n_rows;
+  D.group = M.group;
+  D.depth = M.depth;
+  D.width = M.width;
+  D.stored = static_cast<int64_t>(M.col.size());
+  D.ptr = ar.upload(M.ptr);
+  D.col = ar.upload(M.col);
+  D.val = ar.upload(M.val);
   return D;
 }
 
@@ -198,6 +215,48 @@ class Precond final : public PrecondBase {
     const int nl = static_cast<int>(hl.size());
     lv_.resize(nl);
     const double sv = sizeof(T);
+    // host image of the stage-2 matrix (SELL-64 in block-colour order, with a
+    // flag on columns of earlier colours), built while the levels are prepared
+    struct Stage2Image {
+      std::vector<int32_t> sp, col;
+      std::vector<int64_t> pos, diag_pos;
+      std::vector<double> bytes;
+    };
+    auto stage2_task = std::async(std::launch::async, [&]() {
+      Stage2Image S;
+      const int32_t n = n_b;
+      const int32_t ns = (n + kWave - 1) / kWave;
+      S.sp.assign(ns + 1, 0);
+      for (int32_t s2 = 0; s2 < ns; ++s2) {
+        int32_t w = 0;
+        for (int32_t q = s2 * kWave; q < std::min(n, (s2 + 1) * kWave); ++q) {
+          const int32_t i = bperm[q];
+          w = std::max(w, h_row_ptr[i + 1] - h_row_ptr[i]);
+        }
+        S.sp[s2 + 1] = S.sp[s2] + w;
+      }
+      const int64_t slots = S.sp[ns];
+      S.col.assign(static_cast<size_t>(slots) * kWave, kPadCol);
+      S.pos.resize(h_col.size());
+      S.diag_pos.resize(n);
+      S.bytes.assign(bcoff.size() > 0 ? bcoff.size() - 1 : 0, 0.0);
+      for (int32_t q = 0; q < n; ++q) {
+        const int32_t i = bperm[q], s2 = q / kWave, lane = q % kWave;
+        int32_t t = S.sp[s2];
+        const int cidx = bcolour[i];
+        for (int32_t k = h_row_ptr[i]; k < h_row_ptr[i + 1]; ++k, ++t) {
+          const size_t e = static_cast<size_t>(t) * kWave + lane;
+          const int32_t j = h_col[k];
+          const bool earlier = bcolour[j] < bcolour[i];
+          S.col[e] = j | (earlier ? kEarlierBit : 0);
+          S.pos[k] = static_cast<int64_t>(e);
+          if (j == i) S.diag_pos[q] = k;
+          S.bytes[cidx] += (earlier ? 9.0 : 3.0) * sv + 4.0;
+        }
+        S.bytes[cidx] += 24.0 + 13.0 * sv;
+      }
+      return S;
+    });
     std::vector<std::vector<int32_t>> inv(nl);
     for (int l = 0; l < nl; ++l) inv[l] = inverse_perm(hl[l].perm);
     // First level of the one-workgroup tail: every level from it down has at
@@ -217,10 +276,48 @@ class Precond final : public PrecondBase {
     if (lds_for(tail_) > lds_limit)
       throw Error(CPR_ERR_INVALID_ARG, "the coarsest level does not fit one workgroup's LDS (lower coarse_max)");
     tail_lds_ = lds_for(tail_);
+    // host images of every smoothed level, built concurrently, then uploaded
+    struct LevelImage {
+      HostMat<T> A, P, R;
+      std::vector<T> diag;
+      int64_t nnz_p = 0, nnz_r = 0;
+      std::vector<double> colour_bytes;
+    };
+    std::vector<std::future<LevelImage>> images;
+    for (int l = 0; l + 1 < nl; ++l)
+      images.push_back(std::async(std::launch::async, [&, l]() {
+        LevelImage I;
+        const HostLevel& H = hl[l];
+        const bool in_tail = l >= tail_;
+        const int32_t n = H.A.n_rows;
+        I.A = build_mat<T>(H.A, H.perm, inv[l], prm.row_layout, in_tail);
+        I.diag.resize(n);
+        for (int32_t p = 0; p < n; ++p) {
+          const int32_t i = H.perm[p];
+          double d = 0.0;
+          for (int32_t q = H.A.ptr[i]; q < H.A.ptr[i + 1]; ++q)
+            if (H.A.col[q] == i) d = H.A.val[q];
+          I.diag[p] = static_cast<T>(d);
+        }
+        I.P = build_mat<T>(H.P, H.perm, inv[l + 1], prm.row_layout, in_tail);
+        const HostCsr R = transpose(H.P);
+        I.R = build_mat<T>(R, hl[l + 1].perm, inv[l], prm.row_layout, in_tail);
+        I.nnz_p = H.P.nnz();
+        I.nnz_r = R.nnz();
+        for (size_t c = 0; c + 1 < H.coff.size(); ++c) {
+          int64_t nz = 0;
+          for (int32_t p = H.coff[c]; p < H.coff[c + 1]; ++p) {
+            const int32_t i = H.perm[p];
+            nz += H.A.ptr[i + 1] - H.A.ptr[i];
+          }
+          const int64_t rows = H.coff[c + 1] - H.coff[c];
+          I.colour_bytes.push_back(nz * (sv + 4.0) + 4.0 * rows + 4.0 * rows * sv);
+        }
+        return I;
+      }));
     for (int l = 0; l < nl; ++l) {
       Level& L = lv_[l];
       const HostLevel& H = hl[l];
-      const bool in_tail = l >= tail_;
       L.n = H.A.n_rows;
       L.nnz = H.A.nnz();
       L.coff = H.coff;
@@ -228,33 +325,17 @@ class Precond final : public PrecondBase {
       L.x = ar_.alloc<T>(L.n);
       L.b = ar_.alloc<T>(L.n);
       if (l + 1 < nl) {
-        L.A = upload_mat<T>(ar_, H.A, H.perm, inv[l], prm.row_layout, in_tail);
-        std::vector<T> dg(L.n);
-        for (int32_t p = 0; p < L.n; ++p) {
-          const int32_t i = H.perm[p];
-          double d = 0.0;
-          for (int32_t q = H.A.ptr[i]; q < H.A.ptr[i + 1]; ++q)
-            if (H.A.col[q] == i) d = H.A.val[q];
-          dg[p] = static_cast<T>(d);
-        }
-        L.diag = ar_.upload(dg);
+        LevelImage I = images[l].get();
+        L.A = upload_mat<T>(ar_, I.A);
+        L.diag = ar_.upload(I.diag);
         L.r = ar_.alloc<T>(L.n);
         L.s0 = ar_.alloc<T>(L.n);
         L.s1 = ar_.alloc<T>(L.n);
-        L.P = upload_mat<T>(ar_, H.P, H.perm, inv[l + 1], prm.row_layout, in_tail);
-        const HostCsr R = transpose(H.P);
-        L.R = upload_mat<T>(ar_, R, hl[l + 1].perm, inv[l], prm.row_layout, in_tail);
-        L.nnz_p = H.P.nnz();
-        L.nnz_r = R.nnz();
-        for (size_t c = 0; c + 1 < L.coff.size(); ++c) {
-          int64_t nz = 0;
-          for (int32_t p = L.coff[c]; p < L.coff[c + 1]; ++p) {
-            const int32_t i = H.perm[p];
-            nz += H.A.ptr[i + 1] - H.A.ptr[i];
-          }
-          const int64_t rows = L.coff[c + 1] - L.coff[c];
-          L.colour_bytes.push_back(nz * (sv + 4.0) + 4.0 * rows + 4.0 * rows * sv);
-        }
+        L.P = upload_mat<T>(ar_, I.P);
+        L.R = upload_mat<T>(ar_, I.R);
+        L.nnz_p = I.nnz_p;
+        L.nnz_r = I.nnz_r;
+        L.colour_bytes = std::move(I.colour_bytes);
       }
     }
     nL_ = lv_.back().n;
@@ -312,36 +393,13 @@ class Precond final : public PrecondBase {
     bcoff_ = bcoff;
     cell_ = ar_.upload(bperm);
     const int32_t n = n_b;
-    const int32_t ns = (n + kWave - 1) / kWave;
-    std::vector<int32_t> sp(ns + 1, 0);
-    for (int32_t s2 = 0; s2 < ns; ++s2) {
-      int32_t w = 0;
-      for (int32_t q = s2 * kWave; q < std::min(n, (s2 + 1) * kWave); ++q) {
-        const int32_t i = bperm[q];
-        w = std::max(w, h_row_ptr[i + 1] - h_row_ptr[i]);
-      }
-      sp[s2 + 1] = sp[s2] + w;
-    }
-    const int64_t slots = sp[ns];
-    std::vector<int32_t> col(static_cast<size_t>(slots) * kWave, kPadCol);
-    std::vector<int64_t> pos(h_col.size());
-    std::vector<int64_t> diag_pos(n);
-    stage2_bytes_.assign(bcoff.size() > 0 ? bcoff.size() - 1 : 0, 0.0);
-    for (int32_t q = 0; q < n; ++q) {
-      const int32_t i = bperm[q], s2 = q / kWave, lane = q % kWave;
-      int32_t t = sp[s2];
-      int cidx = bcolour[i];
-      for (int32_t k = h_row_ptr[i]; k < h_row_ptr[i + 1]; ++k, ++t) {
-        const size_t e = static_cast<size_t>(t) * kWave + lane;
-        const int32_t j = h_col[k];
-        const bool earlier = bcolour[j] < bcolour[i];
-        col[e] = j | (earlier ? kEarlierBit : 0);
-        pos[k] = static_cast<int64_t>(e);
-        if (j == i) diag_pos[q] = k;
-        stage2_bytes_[cidx] += (earlier ? 9.0 : 3.0) * sv + 4.0;
-      }
-      stage2_bytes_[cidx] += 24.0 + 13.0 * sv;
-    }
+    Stage2Image S2 = stage2_task.get();
+    std::vector<int32_t>& sp = S2.sp;
+    std::vector<int32_t>& col = S2.col;
+    std::vector<int64_t>& pos = S2.pos;
+    std::vector<int64_t>& diag_pos = S2.diag_pos;
+    stage2_bytes_ = std::move(S2.bytes);
+    const int64_t slots = sp.back();
     fine_.n_rows = n;
     fine_.slots = slots;
     fine_.slice_ptr = ar_.upload(sp);

@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <future>
 #include <numeric>
 
@@ -197,6 +199,9 @@ void cpr_handle::build_precond() {
     return colour_level(B, h_row_ptr);
   });
   std::vector<std::future<Colouring>> level_tasks;
+  // SETUP phase times (ms), printed to stderr when CPR_SETUP_TRACE is set
+  double t_strength = 0, t_split = 0, t_interp = 0, t_galerkin = 0;
+  const double t_loop0 = now_ms();
 
   HostCsr A;
   A.n_rows = A.n_cols = n_b;
@@ -229,6 +234,7 @@ void cpr_handle::build_precond() {
       d_val = tmp.alloc<double>(cap_nnz);
       d_mask = tmp.alloc<uint8_t>(cap_nnz);
     }
+    double tp = now_ms();
     HIPCHK(hipMemcpyAsync(d_ptr, L.A.ptr.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(d_col, L.A.col.data(), L.A.nnz() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(d_val, L.A.val.data(), L.A.nnz() * sizeof(double), hipMemcpyHostToDevice, stream));
@@ -236,6 +242,8 @@ void cpr_handle::build_precond() {
     L.mask.resize(L.A.nnz());
     HIPCHK(hipMemcpyAsync(L.mask.data(), d_mask, L.A.nnz(), hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
+    t_strength += now_ms() - tp;
+    tp = now_ms();
 
     // colouring of this level (eq. (strong-matrix) pattern) on its own thread
     level_tasks.push_back(std::async(std::launch::async, [Sc = pattern_from_mask(L.A, L.mask, 2),
@@ -243,6 +251,7 @@ void cpr_handle::build_precond() {
     const Pattern S = pattern_from_mask(L.A, L.mask, 1);
     const Pattern ST = transpose_pattern(S);
     rs_split(S, ST, L.cf);
+    t_split += now_ms() - tp;
     int32_t nc = 0;
     for (int8_t c : L.cf) nc += (c == 1);
     if (nc == 0 || static_cast<double>(nc) > 0.9 * n) {
@@ -252,15 +261,21 @@ void cpr_handle::build_precond() {
       hl.push_back(std::move(L));
       break;
     }
+    tp = now_ms();
     if (!rs_interpolation(L.A, L.mask, 1, L.cf, L.P))
       throw Error(CPR_ERR_SINGULAR_COARSE, "zero interpolation denominator");
+    t_interp += now_ms() - tp;
+    tp = now_ms();
     const HostCsr R = transpose(L.P);
     const HostCsr AP = spgemm_ordered(L.A, L.P);
     A = spgemm_ordered(R, AP);
+    t_galerkin += now_ms() - tp;
     hl.push_back(std::move(L));
   }
   tmp.release();
 
+  const double t_loop = now_ms() - t_loop0;
+  double tp = now_ms();
   const int nl = static_cast<int>(hl.size());
   for (int l = 0; l < nl; ++l) {
     HostLevel& L = hl[l];
@@ -287,6 +302,8 @@ void cpr_handle::build_precond() {
 
   // stage-2 block colouring (computed on its own thread since the start)
   Colouring bc = block_task.get();
+  const double t_colour_wait = now_ms() - tp;
+  tp = now_ms();
   block_colour = std::move(bc.colour);
   n_block_colours = bc.n_colours;
   std::vector<int32_t> bperm = std::move(bc.perm), bcoff = std::move(bc.coff);
@@ -297,6 +314,11 @@ void cpr_handle::build_precond() {
   HIPCHK(hipStreamSynchronize(stream));
   values_changed = false;
   last_setup_ms = now_ms() - t0;
+  if (std::getenv("CPR_SETUP_TRACE"))
+    std::fprintf(stderr,
+                 "[cpr setup] %.1f ms: levels %.1f (strength %.1f, split %.1f, interpolation %.1f, galerkin %.1f), "
+                 "colouring wait %.1f, LU + device images %.1f\n",
+                 last_setup_ms, t_loop, t_strength, t_split, t_interp, t_galerkin, t_colour_wait, now_ms() - tp);
 }
 
 void cpr_handle::spmv(const double* x, double* y) {
