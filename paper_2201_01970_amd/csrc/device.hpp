@@ -57,9 +57,24 @@ struct LaunchTimer {
 template <typename TA, typename TX>
 void launch_bsr_spmv(const SellView<TA>& A, const TX* x, const double* b, double* y, hipStream_t s);
 
-// rp[p] = v[3*perm[p]] (pressure restriction, with cast)
+// The first colour of a sweep that starts from x = 0 reads no neighbour: its
+// rows get x_i = b_i / a_ii (the sum over earlier colours is empty).  A kernel
+// that produces b can write these directly: for device rows p < n_first,
+// x[p] = b[p] / diag[p] and snap[p] = x[p] (the sweep's output snapshot), and
+// the sweep then starts at its second colour.  n_first = 0: nothing fused.
 template <typename T>
-void launch_restrict_pressure(int32_t n, const double* v, const int32_t* perm, T* rp, hipStream_t s);
+struct ZeroStart {
+  int32_t n_first = 0;
+  const T* diag = nullptr;
+  T* x = nullptr;
+  T* snap = nullptr;
+};
+
+// rp[p] = v[3 perm[p]] (pressure entries of the level-0 device rows), with
+// the zero-start first colour of level 0 fused (see ZeroStart)
+template <typename T>
+void launch_restrict_pressure(int32_t n, const double* v, const int32_t* perm, T* rp, const ZeroStart<T>& zs,
+                              hipStream_t s);
 
 // pe[perm[p]] = e[p]
 template <typename T>
@@ -99,6 +114,11 @@ void launch_csr_residual(const MatView<T>& A, const T* b, const T* x, T* r, hipS
 // y = A x (sum from 0 in stored order)
 template <typename T>
 void launch_csr_spmv(const MatView<T>& A, const T* x, T* y, hipStream_t s);
+
+// b = R r (sum from 0 in stored order), with the zero-start first colour of
+// the next level fused as above
+template <typename T>
+void launch_csr_restrict(const MatView<T>& R, const T* r, T* b, const ZeroStart<T>& zs, hipStream_t s);
 
 // x_i = x_i + (sum_J p_iJ e_J); snap[i] = x_i
 template <typename T>

@@ -266,15 +266,22 @@ template void launch_gs_colour<float>(const MatView<float>&, const float*, int32
 // MODE 0: y = b - A x (residual; products subtracted from b in stored order)
 // MODE 1: y = A x (sum from 0 in stored order)
 // MODE 2: y = y + (A x), snap = y (prolongation add; the sum from 0 first)
+// MODE 3: y = A x (restriction), and rows of the next level's zero-start
+//         first colour get x = y / a_ii (see ZeroStart)
 template <typename T, int MODE>
 __device__ __forceinline__ void finish_row(int32_t q, T acc, const T* __restrict__ b, T* __restrict__ y,
-                                           T* __restrict__ snap) {
+                                           T* __restrict__ snap, const ZeroStart<T>& zs) {
   if (MODE == 2) {
     const T yn = y[q] + acc;
     y[q] = yn;
     snap[q] = yn;
   } else {
     y[q] = acc;
+    if (MODE == 3 && q < zs.n_first) {
+      const T xn = acc / zs.diag[q];
+      zs.x[q] = xn;
+      zs.snap[q] = xn;
+    }
   }
 }
 
@@ -282,7 +289,7 @@ template <typename T, int U, int MODE>
 __global__ __launch_bounds__(kBlock) void k_rows_sell(int32_t n, int32_t width, const int32_t* __restrict__ slice_ptr,
                                                       const int32_t* __restrict__ col, const T* __restrict__ val,
                                                       const T* __restrict__ b, const T* __restrict__ x,
-                                                      T* __restrict__ y, T* __restrict__ snap) {
+                                                      T* __restrict__ y, T* __restrict__ snap, ZeroStart<T> zs) {
   const int32_t q = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (q >= n) return;
   T acc = (MODE == 0) ? b[q] : (T)0;
@@ -290,14 +297,14 @@ __global__ __launch_bounds__(kBlock) void k_rows_sell(int32_t n, int32_t width, 
     const T prod = (c >= 0) ? a * x[c] : (T)0;
     acc = (MODE == 0) ? (acc - prod) : (acc + prod);
   });
-  finish_row<T, MODE>(q, acc, b, y, snap);
+  finish_row<T, MODE>(q, acc, b, y, snap, zs);
 }
 
 template <typename T, int G, int CH, int MODE>
 __global__ __launch_bounds__(kBlock) void k_rows_grp(int32_t n, const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ col, const T* __restrict__ val,
                                                      const T* __restrict__ b, const T* __restrict__ x,
-                                                     T* __restrict__ y, T* __restrict__ snap) {
+                                                     T* __restrict__ y, T* __restrict__ snap, ZeroStart<T> zs) {
   const int32_t q = (blockIdx.x * kBlock + threadIdx.x) / G;  // round-robin over XCDs, as k_gs_grp
   const int lane = threadIdx.x % G;
   if (q >= n) return;
@@ -319,87 +326,99 @@ __global__ __launch_bounds__(kBlock) void k_rows_grp(int32_t n, const int32_t* _
     for (int u = 0; u < CH; ++u)
       if (u < nch) acc = group_chunk<T, G, MODE == 0>(acc, prod[u], lane);
   }
-  if (lane == last_lane<G>()) finish_row<T, MODE>(q, acc, b, y, snap);
+  if (lane == last_lane<G>()) finish_row<T, MODE>(q, acc, b, y, snap, zs);
 }
 
 template <typename T, int CH, int MODE>
 __global__ __launch_bounds__(kBlock) void k_rows_q4(int32_t n, const int32_t* __restrict__ rp,
                                                     const int32_t* __restrict__ col, const T* __restrict__ val,
                                                     const T* __restrict__ b, const T* __restrict__ x,
-                                                    T* __restrict__ y, T* __restrict__ snap) {
+                                                    T* __restrict__ y, T* __restrict__ snap, ZeroStart<T> zs) {
   const int32_t q = (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 2);
   const int lane = threadIdx.x & 3;
   if (q >= n) return;
-  // MODE 1 and 2 add: subtract the negated products (the same IEEE operation)
+  // MODE 1, 2 and 3 add: subtract the negated products (the same IEEE operation)
   const T acc = quad_row_sub<T, CH>((MODE == 0) ? b[q] : (T)0, rp[q], rp[q + 1], col, val, lane,
                                     [&](int32_t c, T a) {
                                       const T pr = (c >= 0) ? a * x[c] : (T)0;
                                       return MODE == 0 ? pr : -pr;
                                     });
-  if (lane == 3) finish_row<T, MODE>(q, acc, b, y, snap);
+  if (lane == 3) finish_row<T, MODE>(q, acc, b, y, snap, zs);
 }
 
 template <typename T, int CH, int MODE>
-void launch_rows_q4(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, hipStream_t s) {
+void launch_rows_q4(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, const ZeroStart<T>& zs,
+                    hipStream_t s) {
   hipLaunchKernelGGL((k_rows_q4<T, CH, MODE>), dim3(div_up((int64_t)A.n_rows * 4, kBlock)), dim3(kBlock), 0, s,
-                     A.n_rows, A.ptr, A.col, A.val, b, x, y, snap);
+                     A.n_rows, A.ptr, A.col, A.val, b, x, y, snap, zs);
 }
 
 template <typename T, int G, int CH, int MODE>
-void launch_rows_grp(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, hipStream_t s) {
+void launch_rows_grp(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, const ZeroStart<T>& zs,
+                     hipStream_t s) {
   hipLaunchKernelGGL((k_rows_grp<T, G, CH, MODE>), dim3(div_up((int64_t)A.n_rows * G, kBlock)), dim3(kBlock), 0, s,
-                     A.n_rows, A.ptr, A.col, A.val, b, x, y, snap);
+                     A.n_rows, A.ptr, A.col, A.val, b, x, y, snap, zs);
 }
 
 template <typename T, int U, int MODE>
-void launch_rows_sell(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, hipStream_t s) {
+void launch_rows_sell(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, const ZeroStart<T>& zs,
+                      hipStream_t s) {
   hipLaunchKernelGGL((k_rows_sell<T, U, MODE>), dim3(div_up(A.n_rows, kBlock)), dim3(kBlock), 0, s, A.n_rows, A.width,
-                     A.ptr, A.col, A.val, b, x, y, snap);
+                     A.ptr, A.col, A.val, b, x, y, snap, zs);
 }
 
 template <typename T, int MODE>
-void launch_rows(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, hipStream_t s) {
+void launch_rows(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, const ZeroStart<T>& zs,
+                 hipStream_t s) {
   if (A.n_rows == 0) return;
   if (A.group == 1 && A.depth <= 8)
-    launch_rows_sell<T, 8, MODE>(A, b, x, y, snap, s);
+    launch_rows_sell<T, 8, MODE>(A, b, x, y, snap, zs, s);
   else if (A.group == 1 && A.depth <= 16)
-    launch_rows_sell<T, 16, MODE>(A, b, x, y, snap, s);
+    launch_rows_sell<T, 16, MODE>(A, b, x, y, snap, zs, s);
   else if (A.group == 1)
-    launch_rows_sell<T, 32, MODE>(A, b, x, y, snap, s);
+    launch_rows_sell<T, 32, MODE>(A, b, x, y, snap, zs, s);
   else if (A.group == 4 && A.depth <= 2)
-    launch_rows_q4<T, 2, MODE>(A, b, x, y, snap, s);
+    launch_rows_q4<T, 2, MODE>(A, b, x, y, snap, zs, s);
   else if (A.group == 4 && A.depth <= 4)
-    launch_rows_q4<T, 4, MODE>(A, b, x, y, snap, s);
+    launch_rows_q4<T, 4, MODE>(A, b, x, y, snap, zs, s);
   else if (A.group == 4)
-    launch_rows_q4<T, 8, MODE>(A, b, x, y, snap, s);
+    launch_rows_q4<T, 8, MODE>(A, b, x, y, snap, zs, s);
   else if (A.group == 16 && A.depth <= 4)
-    launch_rows_grp<T, 16, 4, MODE>(A, b, x, y, snap, s);
+    launch_rows_grp<T, 16, 4, MODE>(A, b, x, y, snap, zs, s);
   else if (A.group == 16 && A.depth <= 8)
-    launch_rows_grp<T, 16, 8, MODE>(A, b, x, y, snap, s);
+    launch_rows_grp<T, 16, 8, MODE>(A, b, x, y, snap, zs, s);
   else if (A.group == 16)
-    launch_rows_grp<T, 16, 16, MODE>(A, b, x, y, snap, s);
+    launch_rows_grp<T, 16, 16, MODE>(A, b, x, y, snap, zs, s);
   else if (A.group == 32)
-    launch_rows_grp<T, 32, 4, MODE>(A, b, x, y, snap, s);
+    launch_rows_grp<T, 32, 4, MODE>(A, b, x, y, snap, zs, s);
   else
-    launch_rows_grp<T, 64, 4, MODE>(A, b, x, y, snap, s);
+    launch_rows_grp<T, 64, 4, MODE>(A, b, x, y, snap, zs, s);
   CPR_LAUNCH_CHECK();
 }
 
 template <typename T>
 void launch_csr_residual(const MatView<T>& A, const T* b, const T* x, T* r, hipStream_t s) {
-  launch_rows<T, 0>(A, b, x, r, nullptr, s);
+  launch_rows<T, 0>(A, b, x, r, nullptr, ZeroStart<T>{}, s);
 }
 template <typename T>
 void launch_csr_spmv(const MatView<T>& A, const T* x, T* y, hipStream_t s) {
-  launch_rows<T, 1>(A, nullptr, x, y, nullptr, s);
+  launch_rows<T, 1>(A, nullptr, x, y, nullptr, ZeroStart<T>{}, s);
+}
+template <typename T>
+void launch_csr_restrict(const MatView<T>& R, const T* r, T* b, const ZeroStart<T>& zs, hipStream_t s) {
+  if (zs.n_first > 0)
+    launch_rows<T, 3>(R, nullptr, r, b, nullptr, zs, s);
+  else
+    launch_rows<T, 1>(R, nullptr, r, b, nullptr, zs, s);
 }
 template <typename T>
 void launch_prolong_add(const MatView<T>& P, const T* e, T* x, T* snap, hipStream_t s) {
-  launch_rows<T, 2>(P, nullptr, e, x, snap, s);
+  launch_rows<T, 2>(P, nullptr, e, x, snap, ZeroStart<T>{}, s);
 }
 #define CPR_INST_ROWS(T)                                                                               \
   template void launch_csr_residual<T>(const MatView<T>&, const T*, const T*, T*, hipStream_t);     \
   template void launch_csr_spmv<T>(const MatView<T>&, const T*, T*, hipStream_t);                    \
+  template void launch_csr_restrict<T>(const MatView<T>&, const T*, T*, const ZeroStart<T>&, hipStream_t); \
   template void launch_prolong_add<T>(const MatView<T>&, const T*, T*, T*, hipStream_t);
 CPR_INST_ROWS(double)
 CPR_INST_ROWS(float)

@@ -89,20 +89,29 @@ template void launch_bsr_spmv<double, float>(const SellView<double>&, const floa
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_restrict_pressure(int32_t n, const double* __restrict__ v,
                                                               const int32_t* __restrict__ perm,
-                                                              T* __restrict__ rp) {
+                                                              T* __restrict__ rp, ZeroStart<T> zs) {
   const int32_t p = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (p >= n) return;
-  rp[p] = (T)v[3 * (int64_t)perm[p]];
+  const T b = (T)v[3 * (int64_t)perm[p]];
+  rp[p] = b;
+  if (p < zs.n_first) {  // first colour of a zero-start sweep: x = b / a_ii
+    const T xn = b / zs.diag[p];
+    zs.x[p] = xn;
+    zs.snap[p] = xn;
+  }
 }
 
 template <typename T>
-void launch_restrict_pressure(int32_t n, const double* v, const int32_t* perm, T* rp, hipStream_t s) {
+void launch_restrict_pressure(int32_t n, const double* v, const int32_t* perm, T* rp, const ZeroStart<T>& zs,
+                              hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL((k_restrict_pressure<T>), dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, v, perm, rp);
+  hipLaunchKernelGGL((k_restrict_pressure<T>), dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, v, perm, rp, zs);
   CPR_LAUNCH_CHECK();
 }
-template void launch_restrict_pressure<double>(int32_t, const double*, const int32_t*, double*, hipStream_t);
-template void launch_restrict_pressure<float>(int32_t, const double*, const int32_t*, float*, hipStream_t);
+template void launch_restrict_pressure<double>(int32_t, const double*, const int32_t*, double*,
+                                               const ZeroStart<double>&, hipStream_t);
+template void launch_restrict_pressure<float>(int32_t, const double*, const int32_t*, float*,
+                                              const ZeroStart<float>&, hipStream_t);
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scatter(int32_t n, const T* __restrict__ e,

@@ -424,8 +424,9 @@ class Precond final : public PrecondBase {
   void apply(const double* v, void* zv, hipStream_t s) override {
     T* z = static_cast<T*>(zv);
     Level& L0 = lv_[0];
-    launch_restrict_pressure<T>(L0.n, v, L0.perm, L0.b, s);
-    vcycle(0, s);
+    const ZeroStart<T> zs = zero_start(0);
+    launch_restrict_pressure<T>(L0.n, v, L0.perm, L0.b, zs, s);
+    vcycle(0, s, zs.n_first > 0);
     launch_scatter<T>(L0.n, L0.x, L0.perm, pe_, s);
     const SellView<T> F = fine_.view();
     for (size_t c = 0; c + 1 < bcoff_.size(); ++c) {
@@ -438,7 +439,7 @@ class Precond final : public PrecondBase {
   void vcycle_own(const double* r, double* e, hipStream_t s) override {
     Level& L0 = lv_[0];
     launch_gather<double, T>(L0.n, r, L0.perm, L0.b, s);
-    vcycle(0, s);
+    vcycle(0, s, false);
     launch_scatter_cast<T, double>(L0.n, L0.x, L0.perm, e, s);
   }
 
@@ -461,19 +462,35 @@ class Precond final : public PrecondBase {
   int64_t bytes() const override { return ar_.bytes(); }
 
  private:
-  void sweep(int l, int cur, bool zero, hipStream_t s) {
+  // The first pre-sweep of a level below the tail's start begins from x = 0;
+  // its first colour is then fused into the kernel that writes the level's b.
+  ZeroStart<T> zero_start(int l) const {
+    ZeroStart<T> zs;
+    if (l < tail_ && pre_ > 0 && lv_[l].coff.size() > 1) {
+      const Level& L = lv_[l];
+      zs.n_first = L.coff[1];
+      zs.diag = L.diag;
+      zs.x = L.x;
+      zs.snap = L.s1;  // the output snapshot of the first sweep (S[cur ^ 1] with cur = 0)
+    }
+    return zs;
+  }
+
+  // first_done: the first colour was already computed by the producer of b
+  void sweep(int l, int cur, bool zero, hipStream_t s, bool first_done = false) {
     Level& L = lv_[l];
     T* S[2] = {L.s0, L.s1};
     const MatView<T> A = L.A.view();
     const int kind = l == 0 ? CPR_KSTAT_SMOOTH_L0 : CPR_KSTAT_SMOOTH_COARSE;
-    for (size_t c = 0; c + 1 < L.coff.size(); ++c) {
+    for (size_t c = first_done ? 1 : 0; c + 1 < L.coff.size(); ++c) {
       if (timer) timer->begin(kind, s);
       launch_gs_colour<T>(A, L.diag, L.coff[c], L.coff[c + 1], L.b, L.x, S[cur], S[cur ^ 1], zero, s);
       if (timer) timer->end(kind, s, L.colour_bytes[c]);
     }
   }
 
-  void vcycle(int l, hipStream_t s) {
+  // first_done: colour 0 of the first pre-sweep was fused into the producer of b
+  void vcycle(int l, hipStream_t s, bool first_done) {
     Level& L = lv_[l];
     const int nl = static_cast<int>(lv_.size());
     if (l == tail_) {
@@ -486,7 +503,7 @@ class Precond final : public PrecondBase {
     int cur = 0;
     if (pre_ == 0) launch_fill<T>(L.n, (T)0, L.x, s);
     for (int w = 0; w < pre_; ++w) {
-      sweep(l, cur, w == 0, s);
+      sweep(l, cur, w == 0, s, w == 0 && first_done);
       cur ^= 1;
     }
     Level& C = lv_[l + 1];
@@ -494,10 +511,12 @@ class Precond final : public PrecondBase {
     if (timer) timer->begin(kind, s);
     launch_csr_residual<T>(L.A.view(), L.b, L.x, L.r, s);
     if (timer) timer->end(kind, s, L.nnz * (sv + 4) + 4.0 * L.n + 3.0 * L.n * sv);
+    const ZeroStart<T> zs = zero_start(l + 1);
     if (timer) timer->begin(kind, s);
-    launch_csr_spmv<T>(L.R.view(), L.r, C.b, s);
-    if (timer) timer->end(kind, s, L.nnz_r * (sv + 4) + 4.0 * C.n + L.n * sv + C.n * sv);
-    vcycle(l + 1, s);
+    launch_csr_restrict<T>(L.R.view(), L.r, C.b, zs, s);
+    if (timer)
+      timer->end(kind, s, L.nnz_r * (sv + 4) + 4.0 * C.n + L.n * sv + C.n * sv + 3.0 * sv * zs.n_first);
+    vcycle(l + 1, s, zs.n_first > 0);
     T* S[2] = {L.s0, L.s1};
     if (timer) timer->begin(kind, s);
     launch_prolong_add<T>(L.P.view(), C.x, L.x, S[cur], s);
