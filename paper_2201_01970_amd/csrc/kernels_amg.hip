@@ -118,9 +118,10 @@ __global__ __launch_bounds__(kBlock) void k_gs_sell(int32_t lo, int32_t hi, int3
   const int32_t q = base + xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (q < lo || q >= hi) return;
   T s = b[q];
+  const T d = diag[q];  // requested with b, off the row's dependent chain
   sell_row<T, U>(q, width, slice_ptr, col, val,
                  [&](int32_t c, T a) { s = s - gs_prod<T, ZERO>(q, c, a, lo, hi, x, s_in); });
-  const T xn = s / diag[q];
+  const T xn = s / d;
   x[q] = xn;
   s_out[q] = xn;
 }
@@ -142,6 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_grp(int32_t lo, int32_t hi, const
   const int32_t q = lo + g;
   if (q >= hi) return;
   T s = b[q];
+  const T d = diag[q];  // requested with b, off the row's dependent chain
   const int32_t p0 = rp[q], p1 = rp[q + 1];
   for (int32_t p = p0; p < p1; p += G * CH) {
     // chunks this row still has (uniform across the group)
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_grp(int32_t lo, int32_t hi, const
       if (u < nch) s = group_chunk<T, G, true>(s, prod[u], lane);
   }
   if (lane == last_lane<G>()) {
-    const T xn = s / diag[q];
+    const T xn = s / d;
     x[q] = xn;
     s_out[q] = xn;
   }
@@ -191,10 +193,11 @@ __global__ __launch_bounds__(kBlock) void k_gs_q4(int32_t lo, int32_t hi, const 
   const int32_t q = lo + (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 2);
   const int lane = threadIdx.x & 3;
   if (q >= hi) return;
+  const T d = diag[q];  // requested with b, off the row's dependent chain
   const T s = quad_row_sub<T, CH>(b[q], rp[q], rp[q + 1], col, val, lane,
                                   [&](int32_t c, T a) { return gs_prod<T, ZERO>(q, c, a, lo, hi, x, s_in); });
   if (lane == 3) {
-    const T xn = s / diag[q];
+    const T xn = s / d;
     x[q] = xn;
     s_out[q] = xn;
   }

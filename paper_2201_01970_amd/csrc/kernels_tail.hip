@@ -39,6 +39,7 @@ __device__ __forceinline__ void tail_colour(const TailLevel<T>& L, T* V, int32_t
   const auto col = gmem(L.a_col);
   const auto val = gmem(L.a_val);
   for (int32_t q = lo + (int32_t)(threadIdx.x >> 2); q < hi; q += kTailRows) {
+    const T d = gmem(L.diag)[q];  // requested with the row pointers, off the dependent chain
     // branch-free gather: an entry that does not contribute reads row q's own
     // value and its product is replaced by 0
     const T s = quad_row_sub<T, tail_chunks<T>()>(b[q], rp[q], rp[q + 1], col, val, lane, [&](int32_t c, T a) {
@@ -49,7 +50,7 @@ __device__ __forceinline__ void tail_colour(const TailLevel<T>& L, T* V, int32_t
       return use ? a * xv : (T)0;
     });
     if (lane == 3) {
-      const T xn = s / gmem(L.diag)[q];
+      const T xn = s / d;
       x[q] = xn;
       s_out[q] = xn;
     }
