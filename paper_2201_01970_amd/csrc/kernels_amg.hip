@@ -271,11 +271,12 @@ template void launch_gs_colour<float>(const MatView<float>&, const float*, int32
 // MODE 2: y = y + (A x), snap = y (prolongation add; the sum from 0 first)
 // MODE 3: y = A x (restriction), and rows of the next level's zero-start
 //         first colour get x = y / a_ii (see ZeroStart)
+// y0: y[q] requested when the row started (MODE 2), off the dependent chain.
 template <typename T, int MODE>
-__device__ __forceinline__ void finish_row(int32_t q, T acc, const T* __restrict__ b, T* __restrict__ y,
-                                           T* __restrict__ snap, const ZeroStart<T>& zs) {
+__device__ __forceinline__ void finish_row(int32_t q, T acc, T y0, T* __restrict__ y, T* __restrict__ snap,
+                                           const ZeroStart<T>& zs) {
   if (MODE == 2) {
-    const T yn = y[q] + acc;
+    const T yn = y0 + acc;
     y[q] = yn;
     snap[q] = yn;
   } else {
@@ -296,11 +297,12 @@ __global__ __launch_bounds__(kBlock) void k_rows_sell(int32_t n, int32_t width, 
   const int32_t q = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (q >= n) return;
   T acc = (MODE == 0) ? b[q] : (T)0;
+  const T y0 = (MODE == 2) ? y[q] : (T)0;
   sell_row<T, U>(q, width, slice_ptr, col, val, [&](int32_t c, T a) {
     const T prod = (c >= 0) ? a * x[c] : (T)0;
     acc = (MODE == 0) ? (acc - prod) : (acc + prod);
   });
-  finish_row<T, MODE>(q, acc, b, y, snap, zs);
+  finish_row<T, MODE>(q, acc, y0, y, snap, zs);
 }
 
 template <typename T, int G, int CH, int MODE>
@@ -312,6 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_grp(int32_t n, const int32_t* _
   const int lane = threadIdx.x % G;
   if (q >= n) return;
   T acc = (MODE == 0) ? b[q] : (T)0;
+  const T y0 = (MODE == 2) ? y[q] : (T)0;
   const int32_t p0 = rp[q], p1 = rp[q + 1];
   for (int32_t p = p0; p < p1; p += G * CH) {
     const int nch = min(CH, (p1 - p + G - 1) / G);
@@ -329,7 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_grp(int32_t n, const int32_t* _
     for (int u = 0; u < CH; ++u)
       if (u < nch) acc = group_chunk<T, G, MODE == 0>(acc, prod[u], lane);
   }
-  if (lane == last_lane<G>()) finish_row<T, MODE>(q, acc, b, y, snap, zs);
+  if (lane == last_lane<G>()) finish_row<T, MODE>(q, acc, y0, y, snap, zs);
 }
 
 template <typename T, int CH, int MODE>
@@ -340,13 +343,14 @@ __global__ __launch_bounds__(kBlock) void k_rows_q4(int32_t n, const int32_t* __
   const int32_t q = (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 2);
   const int lane = threadIdx.x & 3;
   if (q >= n) return;
+  const T y0 = (MODE == 2) ? y[q] : (T)0;
   // MODE 1, 2 and 3 add: subtract the negated products (the same IEEE operation)
   const T acc = quad_row_sub<T, CH>((MODE == 0) ? b[q] : (T)0, rp[q], rp[q + 1], col, val, lane,
                                     [&](int32_t c, T a) {
                                       const T pr = (c >= 0) ? a * x[c] : (T)0;
                                       return MODE == 0 ? pr : -pr;
                                     });
-  if (lane == 3) finish_row<T, MODE>(q, acc, b, y, snap, zs);
+  if (lane == 3) finish_row<T, MODE>(q, acc, y0, y, snap, zs);
 }
 
 template <typename T, int CH, int MODE>

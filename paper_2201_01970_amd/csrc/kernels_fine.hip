@@ -152,6 +152,12 @@ __global__ __launch_bounds__(kBlock) void k_stage2(int32_t lo, int32_t hi, const
   const int32_t slice = q >> 6, lane = q & 63;
   const int64_t i = cell[q];
   T t0 = (T)v[3 * i], t1 = (T)v[3 * i + 1], t2 = (T)v[3 * i + 2];
+  // D^-1 of this cell and its pressure correction, requested with the row's
+  // first loads rather than after the neighbour loop
+  T dm[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) dm[e] = dinv[q + e * (int64_t)ld];
+  const T pei = pe[i];
   const int32_t s0 = slice_ptr[slice], s1 = slice_ptr[slice + 1];
   for (int32_t t = s0; t < s1; t += kStage2Unroll) {
     // column words of a few slots first, then their value planes and vector
@@ -182,12 +188,11 @@ __global__ __launch_bounds__(kBlock) void k_stage2(int32_t lo, int32_t hi, const
       }
     }
   }
-  const T* d = dinv + q;
   T d0 = (T)0, d1 = (T)0, d2 = (T)0;
-  d0 = d0 + d[0 * (int64_t)ld] * t0; d0 = d0 + d[1 * (int64_t)ld] * t1; d0 = d0 + d[2 * (int64_t)ld] * t2;
-  d1 = d1 + d[3 * (int64_t)ld] * t0; d1 = d1 + d[4 * (int64_t)ld] * t1; d1 = d1 + d[5 * (int64_t)ld] * t2;
-  d2 = d2 + d[6 * (int64_t)ld] * t0; d2 = d2 + d[7 * (int64_t)ld] * t1; d2 = d2 + d[8 * (int64_t)ld] * t2;
-  z[3 * i] = pe[i] + d0;
+  d0 = d0 + dm[0] * t0; d0 = d0 + dm[1] * t1; d0 = d0 + dm[2] * t2;
+  d1 = d1 + dm[3] * t0; d1 = d1 + dm[4] * t1; d1 = d1 + dm[5] * t2;
+  d2 = d2 + dm[6] * t0; d2 = d2 + dm[7] * t1; d2 = d2 + dm[8] * t2;
+  z[3 * i] = pei + d0;
   z[3 * i + 1] = d1;
   z[3 * i + 2] = d2;
 }

@@ -67,6 +67,7 @@ __device__ __forceinline__ void tail_rows(int32_t n, const int32_t* rp_, const i
   const auto col = gmem(col_);
   const auto val = gmem(val_);
   for (int32_t q = (int32_t)(threadIdx.x >> 2); q < n; q += kTailRows) {
+    const T y0 = (MODE == 2) ? y[q] : (T)0;
     // addition runs as subtraction of the negated products (the same IEEE operation)
     const T acc = quad_row_sub<T, tail_chunks<T>()>((MODE == 0) ? b[q] : (T)0, rp[q], rp[q + 1], col, val, lane,
                                                [&](int32_t c, T a) {
@@ -76,7 +77,7 @@ __device__ __forceinline__ void tail_rows(int32_t n, const int32_t* rp_, const i
                                                });
     if (lane == 3) {
       if (MODE == 2) {
-        const T yn = y[q] + acc;
+        const T yn = y0 + acc;
         y[q] = yn;
         snap[q] = yn;
       } else {
