@@ -155,8 +155,8 @@ cpr_status cpr_setup(const cpr_bsr* A, const cpr_params* p, void* hip_stream, cp
     if (prm.restart < 1 || prm.restart > 256 || prm.max_restarts < 1 || prm.coarse_max < 1 || prm.max_levels < 1 ||
         prm.pre_sweeps < 0 || prm.post_sweeps < 0 || !(prm.theta_rs >= 0.0) || !(prm.theta_color >= 0.0) ||
         prm.reuse_mode < 0 || prm.reuse_mode > 2 || prm.tail_nnz < 0 ||
-        !(prm.row_layout == 0 || prm.row_layout == 1 || prm.row_layout == 4 || prm.row_layout == 16 ||
-          prm.row_layout == 32 || prm.row_layout == 64))
+        !(prm.row_layout == 0 || prm.row_layout == 1 || prm.row_layout == 2 || prm.row_layout == 4 ||
+          prm.row_layout == 16 || prm.row_layout == 32 || prm.row_layout == 64))
       throw Error(CPR_ERR_INVALID_ARG, "invalid parameters");
     h = new cpr_handle();
     h->prm = prm;

@@ -203,6 +203,38 @@ __global__ __launch_bounds__(kBlock) void k_gs_q4(int32_t lo, int32_t hi, const 
   }
 }
 
+// 16 lanes per row, four contiguous entries per lane (quad-vector CSR data).
+template <typename T, int CH, bool ZERO>
+__global__ __launch_bounds__(kBlock) void k_gs_v16(int32_t lo, int32_t hi, const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                   const T* __restrict__ diag, const T* __restrict__ b,
+                                                   T* __restrict__ x, const T* __restrict__ s_in,
+                                                   T* __restrict__ s_out) {
+  const int32_t q = lo + (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 4);  // round-robin, as k_gs_grp
+  const int lane = threadIdx.x & 15;
+  if (q >= hi) return;
+  const T d = diag[q];  // requested with b, off the row's dependent chain
+  const T s = row16v4_sub<T, CH>(b[q], rp[q], rp[q + 1], col, val, lane,
+                                 [&](int32_t c, T a) { return gs_prod<T, ZERO>(q, c, a, lo, hi, x, s_in); });
+  if (lane == 15) {
+    const T xn = s / d;
+    x[q] = xn;
+    s_out[q] = xn;
+  }
+}
+
+template <typename T, int CH>
+void launch_gs_v16(const MatView<T>& A, const T* diag, int32_t lo, int32_t hi, const T* b, T* x, const T* s_in,
+                   T* s_out, bool zero_start, hipStream_t s) {
+  const int grid = div_up((int64_t)(hi - lo) * 16, kBlock);
+  if (zero_start)
+    hipLaunchKernelGGL((k_gs_v16<T, CH, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag, b,
+                       x, s_in, s_out);
+  else
+    hipLaunchKernelGGL((k_gs_v16<T, CH, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag,
+                       b, x, s_in, s_out);
+}
+
 template <typename T, int CH>
 void launch_gs_q4(const MatView<T>& A, const T* diag, int32_t lo, int32_t hi, const T* b, T* x, const T* s_in,
                   T* s_out, bool zero_start, hipStream_t s) {
@@ -239,6 +271,15 @@ void launch_gs_colour(const MatView<T>& A, const T* diag, int32_t lo, int32_t hi
       launch_gs_sell<T, 16>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
     else
       launch_gs_sell<T, 32>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
+  } else if (A.group == 2) {
+    if (A.depth <= 1)
+      launch_gs_v16<T, 1>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
+    else if (A.depth <= 2)
+      launch_gs_v16<T, 2>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
+    else if (A.depth <= 4)
+      launch_gs_v16<T, 4>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
+    else
+      launch_gs_v16<T, 8>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
   } else if (A.group == 4) {
     if (A.depth <= 2)
       launch_gs_q4<T, 2>(A, diag, lo, hi, b, x, s_in, s_out, zero_start, s);
@@ -354,6 +395,31 @@ __global__ __launch_bounds__(kBlock) void k_rows_q4(int32_t n, const int32_t* __
 }
 
 template <typename T, int CH, int MODE>
+__global__ __launch_bounds__(kBlock) void k_rows_v16(int32_t n, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                     const T* __restrict__ b, const T* __restrict__ x,
+                                                     T* __restrict__ y, T* __restrict__ snap, ZeroStart<T> zs) {
+  const int32_t q = (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 4);
+  const int lane = threadIdx.x & 15;
+  if (q >= n) return;
+  const T y0 = (MODE == 2) ? y[q] : (T)0;
+  // MODE 1, 2 and 3 add: subtract the negated products (the same IEEE operation)
+  const T acc = row16v4_sub<T, CH>((MODE == 0) ? b[q] : (T)0, rp[q], rp[q + 1], col, val, lane,
+                                   [&](int32_t c, T a) {
+                                     const T pr = (c >= 0) ? a * x[c] : (T)0;
+                                     return MODE == 0 ? pr : -pr;
+                                   });
+  if (lane == 15) finish_row<T, MODE>(q, acc, y0, y, snap, zs);
+}
+
+template <typename T, int CH, int MODE>
+void launch_rows_v16(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, const ZeroStart<T>& zs,
+                     hipStream_t s) {
+  hipLaunchKernelGGL((k_rows_v16<T, CH, MODE>), dim3(div_up((int64_t)A.n_rows * 16, kBlock)), dim3(kBlock), 0, s,
+                     A.n_rows, A.ptr, A.col, A.val, b, x, y, snap, zs);
+}
+
+template <typename T, int CH, int MODE>
 void launch_rows_q4(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, const ZeroStart<T>& zs,
                     hipStream_t s) {
   hipLaunchKernelGGL((k_rows_q4<T, CH, MODE>), dim3(div_up((int64_t)A.n_rows * 4, kBlock)), dim3(kBlock), 0, s,
@@ -384,6 +450,14 @@ void launch_rows(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, con
     launch_rows_sell<T, 16, MODE>(A, b, x, y, snap, zs, s);
   else if (A.group == 1)
     launch_rows_sell<T, 32, MODE>(A, b, x, y, snap, zs, s);
+  else if (A.group == 2 && A.depth <= 1)
+    launch_rows_v16<T, 1, MODE>(A, b, x, y, snap, zs, s);
+  else if (A.group == 2 && A.depth <= 2)
+    launch_rows_v16<T, 2, MODE>(A, b, x, y, snap, zs, s);
+  else if (A.group == 2 && A.depth <= 4)
+    launch_rows_v16<T, 4, MODE>(A, b, x, y, snap, zs, s);
+  else if (A.group == 2)
+    launch_rows_v16<T, 8, MODE>(A, b, x, y, snap, zs, s);
   else if (A.group == 4 && A.depth <= 2)
     launch_rows_q4<T, 2, MODE>(A, b, x, y, snap, zs, s);
   else if (A.group == 4 && A.depth <= 4)

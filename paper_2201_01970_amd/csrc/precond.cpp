@@ -77,7 +77,7 @@ constexpr double kSellAvg = 20.0;
 
 int32_t layout_for(int32_t policy, int32_t n, double avg) {
   if (policy != 0) return policy;
-  return (n >= kSellRows && avg <= kSellAvg) ? 1 : 16;
+  return (n >= kSellRows && avg <= kSellAvg) ? 1 : 2;
 }
 
 // Requests a row keeps in flight: enough that nine rows (or slices) in ten
@@ -97,6 +97,7 @@ int32_t csr_depth(const HostCsr& A, int32_t group) {
   for (int32_t i = 0; i < A.n_rows; ++i) len[i] = A.ptr[i + 1] - A.ptr[i];
   const int32_t w = p90(std::move(len));
   if (group == 4) return w <= 32 ? 2 : (w <= 64 ? 4 : 8);
+  if (group == 2) return w <= 64 ? 1 : (w <= 128 ? 2 : (w <= 256 ? 4 : 8));
   return w <= 64 ? 4 : (w <= 128 ? 8 : 16);
 }
 
@@ -150,7 +151,7 @@ HostMat<T> build_mat(const HostCsr& A, const std::vector<int32_t>& order, const 
   }
   // Quad-vector CSR pads every row to a multiple of four entries (column -1,
   // value 0), so each row starts on a 16-byte boundary of the column array.
-  const int32_t pad = layout == 4 ? 4 : 1;
+  const int32_t pad = (layout == 4 || layout == 2) ? 4 : 1;
   M.ptr.assign(n + 1, 0);
   M.col.reserve(A.nnz() + (pad - 1) * static_cast<size_t>(n));
   M.val.reserve(A.nnz() + (pad - 1) * static_cast<size_t>(n));
