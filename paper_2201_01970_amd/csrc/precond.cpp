@@ -73,11 +73,13 @@ SellHost build_sell(const HostCsr& A, const std::vector<int32_t>& order, const s
 // scale, 16-lane groups win on every Galerkin level with 30-90 entries per row
 // (about 2x faster than 32- or 64-lane groups) and on all small matrices.
 constexpr int32_t kSellRows = 32768;
-constexpr double kSellAvg = 20.0;
+constexpr double kSellAvg = 10.0;
+constexpr double kQuadAvg = 24.0;
 
 int32_t layout_for(int32_t policy, int32_t n, double avg) {
   if (policy != 0) return policy;
-  return (n >= kSellRows && avg <= kSellAvg) ? 1 : 2;
+  if (n >= kSellRows && avg <= kSellAvg) return 1;
+  return avg <= kQuadAvg ? 4 : 2;
 }
 
 // Requests a row keeps in flight: enough that nine rows (or slices) in ten
