@@ -37,52 +37,42 @@ void parallel_chunks(int n_chunks, F&& f) {
 
 int n_workers(int n_chunks) { return std::max(1, std::min(setup_threads(), n_chunks)); }
 
-// Rows [0, n) split into chunks; each chunk appends its rows' entries to its
-// own buffers, which are then concatenated in row order.  The result does not
-// depend on the thread count.
+// Rows [0, n) split into contiguous chunks for parallel_chunks.  Every row's
+// result depends only on that row, so results do not depend on the thread
+// count.
 struct RowChunks {
   int32_t n_rows = 0, n_chunks = 0;
-  std::vector<std::vector<int32_t>> col;
-  std::vector<std::vector<double>> val;
-  std::vector<int32_t> row_len;
   explicit RowChunks(int32_t n) : n_rows(n) {
     n_chunks = static_cast<int32_t>(std::min<int64_t>(std::max<int64_t>(1, n / 2048), 256));
-    col.resize(n_chunks);
-    val.resize(n_chunks);
-    row_len.assign(n, 0);
   }
   int32_t begin(int c) const { return static_cast<int32_t>(static_cast<int64_t>(n_rows) * c / n_chunks); }
   int32_t end(int c) const { return static_cast<int32_t>(static_cast<int64_t>(n_rows) * (c + 1) / n_chunks); }
-  void gather(HostCsr& out) {
-    out.ptr.assign(n_rows + 1, 0);
-    for (int32_t i = 0; i < n_rows; ++i) out.ptr[i + 1] = out.ptr[i] + row_len[i];
-    out.col.resize(out.ptr[n_rows]);
-    out.val.resize(out.ptr[n_rows]);
-    parallel_chunks(n_chunks, [&](int c, int) {
-      const int32_t off = out.ptr[begin(c)];
-      std::copy(col[c].begin(), col[c].end(), out.col.begin() + off);
-      std::copy(val[c].begin(), val[c].end(), out.val.begin() + off);
-    });
-  }
 };
 
 }  // namespace
 
 Pattern pattern_from_mask(const HostCsr& A, const std::vector<uint8_t>& mask, uint8_t bit) {
   Pattern S;
-  S.n = A.n_rows;
-  S.ptr.assign(A.n_rows + 1, 0);
-  for (int32_t i = 0; i < A.n_rows; ++i) {
-    int32_t c = 0;
-    for (int32_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) c += (mask[p] & bit) ? 1 : 0;
-    S.ptr[i + 1] = S.ptr[i] + c;
-  }
-  S.col.resize(S.ptr[A.n_rows]);
-  for (int32_t i = 0; i < A.n_rows; ++i) {
-    int32_t w = S.ptr[i];
-    for (int32_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p)
-      if (mask[p] & bit) S.col[w++] = A.col[p];
-  }
+  const int32_t n = A.n_rows;
+  S.n = n;
+  S.ptr.assign(static_cast<size_t>(n) + 1, 0);
+  RowChunks rc(n);
+  parallel_chunks(rc.n_chunks, [&](int ch, int) {
+    for (int32_t i = rc.begin(ch); i < rc.end(ch); ++i) {
+      int32_t c = 0;
+      for (int32_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) c += (mask[p] & bit) ? 1 : 0;
+      S.ptr[i + 1] = c;
+    }
+  });
+  for (int32_t i = 0; i < n; ++i) S.ptr[i + 1] += S.ptr[i];
+  S.col.resize(S.ptr[n]);
+  parallel_chunks(rc.n_chunks, [&](int ch, int) {
+    for (int32_t i = rc.begin(ch); i < rc.end(ch); ++i) {
+      int32_t w = S.ptr[i];
+      for (int32_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p)
+        if (mask[p] & bit) S.col[w++] = A.col[p];
+    }
+  });
   return S;
 }
 
@@ -355,13 +345,30 @@ bool rs_interpolation(const HostCsr& A, const std::vector<uint8_t>& mask, uint8_
   P.n_cols = nc;
   RowChunks rc(n);
   std::atomic<bool> ok{true};
+  // Row lengths first (a C point interpolates from itself; an F point from
+  // each strong C neighbour, or not at all), then one allocation of P, then
+  // the weights written straight into place.
+  P.ptr.assign(static_cast<size_t>(n) + 1, 0);
+  parallel_chunks(rc.n_chunks, [&](int ch, int) {
+    for (int32_t i = rc.begin(ch); i < rc.end(ch); ++i) {
+      int32_t len = 0;
+      if (cf[i] == C) {
+        len = 1;
+      } else {
+        for (int32_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p)
+          if ((mask[p] & bit) && cf[A.col[p]] == C) ++len;
+      }
+      P.ptr[i + 1] = len;
+    }
+  });
+  for (int32_t i = 0; i < n; ++i) P.ptr[i + 1] += P.ptr[i];
+  P.col.resize(P.ptr[n]);
+  P.val.resize(P.ptr[n]);
   // per-thread marks, indexed by fine row and stamped with the current row
   const int nw = n_workers(rc.n_chunks);
   std::vector<std::vector<int32_t>> in_ci_t(nw);
   std::vector<std::vector<double>> num_t(nw);
   parallel_chunks(rc.n_chunks, [&](int ch, int t) {
-    std::vector<int32_t>& pc = rc.col[ch];
-    std::vector<double>& pv = rc.val[ch];
     if (in_ci_t[t].empty()) {
       in_ci_t[t].assign(n, -1);
       num_t[t].assign(n, 0.0);
@@ -369,12 +376,12 @@ bool rs_interpolation(const HostCsr& A, const std::vector<uint8_t>& mask, uint8_
     std::vector<int32_t>& in_ci = in_ci_t[t];
     std::vector<double>& num = num_t[t];
     for (int32_t i = rc.begin(ch); i < rc.end(ch); ++i) {
-      const size_t before = pc.size();
+      int32_t* pc = P.col.data() + P.ptr[i];
+      double* pv = P.val.data() + P.ptr[i];
       const int32_t a0 = A.ptr[i], a1 = A.ptr[i + 1];
       if (cf[i] == C) {
-        pc.push_back(coarse[i]);
-        pv.push_back(1.0);
-        rc.row_len[i] = 1;
+        pc[0] = coarse[i];
+        pv[0] = 1.0;
         continue;
       }
       bool any_c = false;
@@ -407,17 +414,17 @@ bool rs_interpolation(const HostCsr& A, const std::vector<uint8_t>& mask, uint8_
         }
       }
       if (d == 0.0) ok = false;
+      int32_t w = 0;
       for (int32_t p = a0; p < a1; ++p) {
         const int32_t j = A.col[p];
         if ((mask[p] & bit) && cf[j] == C) {
-          pc.push_back(coarse[j]);
-          pv.push_back(-num[j] / d);
+          pc[w] = coarse[j];
+          pv[w] = -num[j] / d;
+          ++w;
         }
       }
-      rc.row_len[i] = static_cast<int32_t>(pc.size() - before);
     }
   });
-  rc.gather(P);
   return ok;
 }
 
@@ -440,26 +447,50 @@ HostCsr transpose(const HostCsr& A) {
   return T;
 }
 
+// Two passes over row chunks: the number of distinct columns of every result
+// row, then (after one allocation of the result) the values, written straight
+// into place.  Growing per-chunk buffers instead made every thread allocate and
+// fault in fresh pages and serialised them (slower than one thread).
 HostCsr spgemm_ordered(const HostCsr& A, const HostCsr& B) {
   HostCsr Cm;
-  Cm.n_rows = A.n_rows;
+  const int32_t n = A.n_rows;
+  Cm.n_rows = n;
   Cm.n_cols = B.n_cols;
-  RowChunks rc(A.n_rows);
+  Cm.ptr.assign(static_cast<size_t>(n) + 1, 0);
+  RowChunks rc(n);
   const int nw = n_workers(rc.n_chunks);
-  std::vector<std::vector<double>> acc_t(nw);
-  std::vector<std::vector<int32_t>> seen_t(nw), touched_t(nw);
+  std::vector<std::vector<int32_t>> seen_t(nw);
   parallel_chunks(rc.n_chunks, [&](int ch, int t) {
-    std::vector<int32_t>& cc = rc.col[ch];
-    std::vector<double>& cv = rc.val[ch];
-    if (seen_t[t].empty()) {
-      acc_t[t].assign(B.n_cols, 0.0);
-      seen_t[t].assign(B.n_cols, -1);
-    }
-    std::vector<double>& acc = acc_t[t];
     std::vector<int32_t>& seen = seen_t[t];
-    std::vector<int32_t>& touched = touched_t[t];
+    if (seen.empty()) seen.assign(B.n_cols, -1);
     for (int32_t i = rc.begin(ch); i < rc.end(ch); ++i) {
-      touched.clear();
+      int32_t cnt = 0;
+      for (int32_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+        const int32_t k = A.col[p];
+        for (int32_t q = B.ptr[k]; q < B.ptr[k + 1]; ++q) {
+          const int32_t j = B.col[q];
+          if (seen[j] != i) {
+            seen[j] = i;
+            ++cnt;
+          }
+        }
+      }
+      Cm.ptr[i + 1] = cnt;
+    }
+  });
+  for (int32_t i = 0; i < n; ++i) Cm.ptr[i + 1] += Cm.ptr[i];
+  Cm.col.resize(Cm.ptr[n]);
+  Cm.val.resize(Cm.ptr[n]);
+  for (auto& seen : seen_t) std::fill(seen.begin(), seen.end(), -1);
+  std::vector<std::vector<double>> acc_t(nw);
+  parallel_chunks(rc.n_chunks, [&](int ch, int t) {
+    std::vector<int32_t>& seen = seen_t[t];
+    std::vector<double>& acc = acc_t[t];
+    if (seen.empty()) seen.assign(B.n_cols, -1);
+    if (acc.empty()) acc.assign(B.n_cols, 0.0);
+    for (int32_t i = rc.begin(ch); i < rc.end(ch); ++i) {
+      int32_t* cols = Cm.col.data() + Cm.ptr[i];
+      int32_t m = 0;
       for (int32_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
         const int32_t k = A.col[p];
         const double a = A.val[p];
@@ -468,21 +499,17 @@ HostCsr spgemm_ordered(const HostCsr& A, const HostCsr& B) {
           if (seen[j] != i) {
             seen[j] = i;
             acc[j] = 0.0;
-            touched.push_back(j);
+            cols[m++] = j;
           }
           const double prod = a * B.val[q];
           acc[j] = acc[j] + prod;
         }
       }
-      std::sort(touched.begin(), touched.end());
-      for (int32_t j : touched) {
-        cc.push_back(j);
-        cv.push_back(acc[j]);
-      }
-      rc.row_len[i] = static_cast<int32_t>(touched.size());
+      std::sort(cols, cols + m);
+      double* vals = Cm.val.data() + Cm.ptr[i];
+      for (int32_t e = 0; e < m; ++e) vals[e] = acc[cols[e]];
     }
   });
-  rc.gather(Cm);
   return Cm;
 }
 
