@@ -84,6 +84,8 @@ typedef struct {
                              one single-workgroup V-cycle kernel; 0 = never [30000] */
   int32_t row_layout;     /* storage of AMG level matrices: 0 = chosen per matrix from its
                              size and row lengths; 1 = one lane per row (SELL-64) everywhere;
+                             2 = CSR read by 16 lanes per row, four contiguous entries
+                             per lane (rows padded to a multiple of four entries);
                              4 = quad-vector CSR (four lanes per row, rows padded to a
                              multiple of four entries) everywhere; 16/32/64 = CSR read by
                              lane groups of that size everywhere.  Levels run by the

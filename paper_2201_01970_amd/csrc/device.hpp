@@ -1,14 +1,17 @@
 // Device data layouts and kernel launchers of the CPR solve phase (gfx950).
 //
-// Layout: every sparse matrix is stored as SELL-64 ("sliced ELLPACK"): rows are
-// grouped in slices of 64 consecutive rows, one row per lane of a 64-wide
-// wavefront; slice s occupies slots [slice_ptr[s], slice_ptr[s+1]), slot t of a
-// slice holds the t-th stored entry of each of its 64 rows, lane-contiguous,
-// so a wavefront streams each slot with fully coalesced loads while every lane
-// still sums its own row sequentially in stored order.  Rows shorter than the
-// slice width are padded with column -1.  For 3x3 blocks the nine values of a
-// slot are stored as nine lane-contiguous planes (value e of lane l of slot t
-// at (t*9 + e)*64 + l).
+// Layouts.  The fine 3x3 block matrix is stored as SELL-64 ("sliced
+// ELLPACK"): rows are grouped in slices of 64 consecutive rows, one row per
+// lane of a 64-wide wavefront; slice s occupies slots [slice_ptr[s],
+// slice_ptr[s+1]), slot t of a slice holds the t-th stored entry of each of its
+// 64 rows, lane-contiguous, so a wavefront streams each slot with fully
+// coalesced loads while every lane still sums its own row sequentially in
+// stored order.  Rows shorter than the slice width are padded with column -1.
+// The nine values of a slot are stored as nine lane-contiguous planes (value e
+// of lane l of slot t at (t*9 + e)*64 + l).  Scalar AMG matrices (levels, P, R)
+// use SELL-64 too when their rows are short and many, otherwise CSR read by a
+// group of lanes per row (MatView::group); every layout sums each row in its
+// stored order, so all of them give bit-identical results.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,8 +34,11 @@ struct SellView {
   const T* val = nullptr;
 };
 
-// An AMG level matrix (or P, R): group == 1 -> SELL-64 (ptr = slice_ptr),
-// group in {16, 32, 64} -> CSR read by `group` lanes per row (ptr = row_ptr).
+// An AMG level matrix (or P, R): group == 1 -> SELL-64 (ptr = slice_ptr);
+// otherwise CSR (ptr = row_ptr): group 2 -> 16 lanes per row with four
+// contiguous entries per lane, 4 -> quad-vector (four lanes per row, four
+// contiguous entries per lane), 16/32/64 -> that many lanes per row, one entry
+// each.  Groups 2 and 4 need rows padded to a multiple of four entries.
 template <typename T>
 struct MatView {
   int32_t n_rows = 0;
@@ -125,40 +131,52 @@ template <typename T>
 void launch_prolong_add(const MatView<T>& P, const T* e, T* x, T* snap, hipStream_t s);
 
 // One level of the one-workgroup tail of the V-cycle.  Matrices stay in
-// device memory (CSR, rows in colour order); the level's vectors x, b, r and
-// the two sweep snapshots live in LDS for the whole kernel, at element offsets
-// off_* from the start of the vector area.  The first tail level reads b from
-// gb when the kernel starts and writes x to gx when it ends (its parent level
-// restricts into gb and prolongates from gx).  P interpolates from the next
-// level to this one, R restricts this level to the next.
+// device memory (quad-vector CSR, rows in colour order); the level's vectors
+// x, b, r and the two sweep snapshots live in the LDS vector area for the
+// whole kernel, at element offsets off_*.  x, s0 and s1 hold n + 1 entries:
+// entry n is a zero that the sweep matrix (w_col, w_val) points at in place of
+// the diagonal and of padding, with value 0, so a sweep's products need no
+// test for either.  a_col/a_val keep the diagonal (residual).  Colour offsets,
+// the diagonal and the row pointers of A, P and R are part of the LDS image
+// copied in when the kernel starts, at the 32-bit word offsets w_*.  The first
+// tail level reads b from gb when the kernel starts and writes x to gx when it
+// ends (its parent level restricts into gb and prolongates from gx).  P
+// interpolates from the next level to this one, R restricts this level to the
+// next.  When w_wcol >= 0 the sweep matrix is part of the image as well
+// (columns at w_wcol, values at w_wval, both at multiples of four words) and
+// the sweeps read it from LDS.
 template <typename T>
 struct TailLevel {
   int32_t n = 0, ncol = 0;
-  const int32_t* coff = nullptr;
-  const int32_t *a_rp = nullptr, *a_col = nullptr;
-  const T *a_val = nullptr, *diag = nullptr;
-  const int32_t *p_rp = nullptr, *p_col = nullptr;
-  const T* p_val = nullptr;
-  const int32_t *r_rp = nullptr, *r_col = nullptr;
-  const T* r_val = nullptr;
   int32_t off_x = 0, off_b = 0, off_r = 0, off_s0 = 0, off_s1 = 0;
+  int32_t w_coff = 0, w_diag = 0, w_arp = 0, w_prp = 0, w_rrp = 0;
+  int32_t w_wcol = -1, w_wval = -1;
+  const int32_t *a_col = nullptr, *w_col = nullptr, *p_col = nullptr, *r_col = nullptr;
+  const T *a_val = nullptr, *w_val = nullptr, *p_val = nullptr, *r_val = nullptr;
   T* gx = nullptr;
   const T* gb = nullptr;
 };
 
-// LDS layout of the tail: the coarsest solve's FP64 staging first, then the
-// level vectors.  tail_lds_doubles: doubles of the staging for a coarsest level
-// of n_coarse rows; the vector area starts at that many doubles.
-__host__ __device__ inline int64_t tail_lds_doubles(int32_t n_coarse) {
-  return n_coarse <= 64 ? 64 + static_cast<int64_t>(n_coarse) * n_coarse : n_coarse;
-}
+// Where the tail kernel keeps things in LDS (offsets in 32-bit words from the
+// start of its dynamic LDS): the image [0, img_words) copied from device memory
+// when the kernel starts (the coarsest level's FP64 LU factors first when the
+// coarsest level has at most 64 rows, then the per-level diagonals, colour
+// offsets, row pointers and staged sweep matrices, and rperm at w_rperm); the
+// FP64 right-hand side of
+// a coarsest level of more than 64 rows at xs_off; the level vectors at v_off.
+// img_words is a multiple of 4, xs_off and v_off are even.
+struct TailLayout {
+  int32_t img_words = 0, w_rperm = 0, xs_off = 0, v_off = 0;
+  size_t lds_bytes = 0;
+};
 
 // V-cycle of the levels levels[0..nlev-1] (the last one the coarsest, solved
-// with the FP64 LU factors of P A = L U, rperm[i] = source row of row i of P b)
-// in one workgroup with lds_bytes of dynamic LDS.
+// with the FP64 LU factors of P A = L U, rperm[i] = source row of row i of
+// P b; lu is read from the image when n_coarse <= 64, else from device memory)
+// in one workgroup.
 template <typename T>
 void launch_tail_vcycle(const TailLevel<T>* levels, int nlev, int pre, int post, int32_t n_coarse, const double* lu,
-                        const int32_t* rperm, size_t lds_bytes, hipStream_t s);
+                        const uint32_t* img, const TailLayout& lay, hipStream_t s);
 
 // Largest dynamic LDS a workgroup of the tail kernel may use on the current device.
 size_t tail_lds_limit();

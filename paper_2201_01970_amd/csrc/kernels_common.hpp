@@ -133,9 +133,10 @@ __device__ __forceinline__ void load4_vals(gptr<double> val, int32_t e, double a
 // zeros, so it keeps its value; a lane recomputing an already final value
 // reproduces it), so lane 3 holds the chunk's result, rounded exactly as a
 // sequential loop over the row rounds it.  CH chunks are requested at once.
+// Entries of a pass beyond the row's end get column `fill` and value 0.
 template <typename T, int CH, typename ColP, typename ValP, typename Prod>
 __device__ __forceinline__ T quad_row_sub(T s, int32_t p0, int32_t p1, ColP col, ValP val, int lane,
-                                          Prod&& prod) {
+                                          Prod&& prod, int32_t fill = -1) {
   for (int32_t p = p0; p < p1; p += 16 * CH) {
     const int nch = min(CH, (p1 - p + 15) / 16);  // uniform across the quad
     int32_t c[CH][4];
@@ -149,7 +150,7 @@ __device__ __forceinline__ T quad_row_sub(T s, int32_t p0, int32_t p1, ColP col,
       } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          c[u][k] = -1;
+          c[u][k] = fill;
           a[u][k] = (T)0;
         }
       }

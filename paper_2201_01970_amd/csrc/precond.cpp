@@ -3,6 +3,7 @@
 // stage 2 = one forward multi-colour block Gauss-Seidel sweep, fused with the
 // prolongation Pi_P and the residual r = v - A z.
 #include <algorithm>
+#include <cstring>
 #include <future>
 #include <numeric>
 
@@ -188,6 +189,52 @@ DevMat<T> upload_mat(Arena& ar, const HostMat<T>& M) {
   return D;
 }
 
+// Stored entries of A in the quad-vector layout (rows padded to a multiple
+// of four).
+int64_t quad_stored(const HostCsr& A) {
+  int64_t m = 0;
+  for (int32_t i = 0; i < A.n_rows; ++i) m += (A.ptr[i + 1] - A.ptr[i] + 3) / 4 * 4;
+  return m;
+}
+
+// LDS layout of the tail kernel when it starts at level `first` and stages
+// the sweep matrices of the smoothed levels from `staged` down (see
+// TailLayout): the image holds the coarsest LU factors (n_c <= 64), then per
+// smoothed level, from an even word, its diagonal (T), colour offsets and the
+// row pointers of A and P (n + 1 each, rows padded in the quad-vector layout
+// keep their count) and of R (next level's n + 1), then rperm (n_c), padded to
+// a multiple of four words, then per staged level the columns and the values
+// of its sweep matrix (each a multiple of four words).  Vectors: x, b, r, s0,
+// s1 of each smoothed level (5 n + 3 elements: x, s0 and s1 carry the zero
+// entry), x and b of the coarsest level.
+template <typename T>
+TailLayout tail_layout(const std::vector<HostLevel>& hl, int first, int staged) {
+  const int nl = static_cast<int>(hl.size());
+  const int64_t nc = hl[nl - 1].A.n_rows;
+  int64_t w = nc <= kWave ? 2 * nc * nc : 0;
+  int64_t t = 2 * nc;
+  for (int l = first; l + 1 < nl; ++l) {
+    const int64_t n = hl[l].A.n_rows;
+    w += w & 1;
+    w += (n * static_cast<int64_t>(sizeof(T)) + 3) / 4;
+    w += static_cast<int64_t>(hl[l].coff.size()) + 2 * (n + 1) + (hl[l + 1].A.n_rows + 1);
+    t += 5 * n + 3;
+  }
+  TailLayout lay;
+  lay.w_rperm = static_cast<int32_t>(w);
+  w += nc;
+  w = (w + 3) / 4 * 4;
+  for (int l = std::max(first, staged); l + 1 < nl; ++l) {
+    const int64_t m = quad_stored(hl[l].A);
+    w += m + m * static_cast<int64_t>(sizeof(T)) / 4;
+  }
+  lay.img_words = static_cast<int32_t>(w);
+  lay.xs_off = static_cast<int32_t>(w);
+  lay.v_off = static_cast<int32_t>(w + (nc > kWave ? 2 * nc : 0));
+  lay.lds_bytes = 4 * static_cast<size_t>(lay.v_off) + static_cast<size_t>(t) * sizeof(T);
+  return lay;
+}
+
 std::vector<int32_t> inverse_perm(const std::vector<int32_t>& perm) {
   std::vector<int32_t> inv(perm.size());
   for (size_t p = 0; p < perm.size(); ++p) inv[perm[p]] = static_cast<int32_t>(p);
@@ -207,7 +254,6 @@ class Precond final : public PrecondBase {
     DevMat<T> A, P, R;
     T *diag = nullptr, *x = nullptr, *b = nullptr, *r = nullptr, *s0 = nullptr, *s1 = nullptr;
     int32_t* perm = nullptr;
-    int32_t* coff_d = nullptr;
   };
 
   Precond(const cpr_params& prm, int32_t n_b, const std::vector<HostLevel>& hl, const std::vector<double>& lu,
@@ -263,22 +309,20 @@ class Precond final : public PrecondBase {
     std::vector<std::vector<int32_t>> inv(nl);
     for (int l = 0; l < nl; ++l) inv[l] = inverse_perm(hl[l].perm);
     // First level of the one-workgroup tail: every level from it down has at
-    // most tail_nnz stored entries and all their vectors fit the LDS of one
-    // workgroup (five per level, two on the coarsest, after the FP64 staging
-    // of the coarsest solve).
+    // most tail_nnz stored entries and the tail's LDS layout fits one
+    // workgroup.
     const int32_t n_last = hl[nl - 1].A.n_rows;
     const size_t lds_limit = tail_lds_limit();
-    auto lds_for = [&](int first) {
-      size_t v = 2 * static_cast<size_t>(n_last);
-      for (int l = first; l + 1 < nl; ++l) v += 5 * static_cast<size_t>(hl[l].A.n_rows);
-      return static_cast<size_t>(tail_lds_doubles(n_last)) * sizeof(double) + v * sizeof(T);
-    };
+    auto lds_for = [&](int first, int staged) { return tail_layout<T>(hl, first, staged).lds_bytes; };
     tail_ = nl - 1;
     if (prm.tail_nnz > 0)
-      while (tail_ > 0 && hl[tail_ - 1].A.nnz() <= prm.tail_nnz && lds_for(tail_ - 1) <= lds_limit) --tail_;
-    if (lds_for(tail_) > lds_limit)
+      while (tail_ > 0 && hl[tail_ - 1].A.nnz() <= prm.tail_nnz && lds_for(tail_ - 1, nl) <= lds_limit) --tail_;
+    if (lds_for(tail_, nl) > lds_limit)
       throw Error(CPR_ERR_INVALID_ARG, "the coarsest level does not fit one workgroup's LDS (lower coarse_max)");
-    tail_lds_ = lds_for(tail_);
+    // the sweep matrices staged in LDS: as many levels, coarsest first, as fit
+    int staged = nl - 1;
+    while (staged > tail_ && lds_for(tail_, staged - 1) <= lds_limit) --staged;
+    tail_lay_ = tail_layout<T>(hl, tail_, staged);
     // host images of every smoothed level, built concurrently, then uploaded
     struct LevelImage {
       HostMat<T> A, P, R;
@@ -318,6 +362,23 @@ class Precond final : public PrecondBase {
         }
         return I;
       }));
+    // LDS image of the tail: FP64 LU factors of a coarsest level of at most 64
+    // rows, then per level the diagonal, colour offsets and row pointers of A,
+    // P and R, then rperm (layout as in tail_layout)
+    std::vector<uint32_t> img;
+    auto put = [&img](const void* p, size_t bytes) {
+      const size_t w0 = img.size();
+      img.resize(w0 + (bytes + 3) / 4, 0u);
+      std::memcpy(img.data() + w0, p, bytes);
+      return static_cast<int32_t>(w0);
+    };
+    auto align_even = [&img]() {
+      if (img.size() & 1) img.push_back(0u);
+    };
+    if (n_last <= kWave) put(lu.data(), lu.size() * sizeof(double));
+    std::vector<TailLevel<T>> td(nl - tail_);
+    std::vector<std::vector<int32_t>> h_wcol(nl);
+    std::vector<std::vector<T>> h_wval(nl);
     for (int l = 0; l < nl; ++l) {
       Level& L = lv_[l];
       const HostLevel& H = hl[l];
@@ -329,6 +390,31 @@ class Precond final : public PrecondBase {
       L.b = ar_.alloc<T>(L.n);
       if (l + 1 < nl) {
         LevelImage I = images[l].get();
+        if (l >= tail_) {
+          // the sweep matrix of the tail: diagonal and padding point at the
+          // zero entry n with value 0
+          TailLevel<T>& d = td[l - tail_];
+          std::vector<int32_t> wcol(I.A.col.size());
+          std::vector<T> wval(I.A.val.size());
+          for (int32_t p = 0; p < L.n; ++p)
+            for (int32_t k = I.A.ptr[p]; k < I.A.ptr[p + 1]; ++k) {
+              const bool off = I.A.col[k] != kPadCol && I.A.col[k] != p;
+              wcol[k] = off ? I.A.col[k] : L.n;
+              wval[k] = off ? I.A.val[k] : static_cast<T>(0);
+            }
+          d.w_col = ar_.upload(wcol);
+          d.w_val = ar_.upload(wval);
+          if (l >= staged) {
+            h_wcol[l] = std::move(wcol);
+            h_wval[l] = std::move(wval);
+          }
+          align_even();
+          d.w_diag = put(I.diag.data(), I.diag.size() * sizeof(T));
+          d.w_coff = put(H.coff.data(), H.coff.size() * sizeof(int32_t));
+          d.w_arp = put(I.A.ptr.data(), I.A.ptr.size() * sizeof(int32_t));
+          d.w_prp = put(I.P.ptr.data(), I.P.ptr.size() * sizeof(int32_t));
+          d.w_rrp = put(I.R.ptr.data(), I.R.ptr.size() * sizeof(int32_t));
+        }
         L.A = upload_mat<T>(ar_, I.A);
         L.diag = ar_.upload(I.diag);
         L.r = ar_.alloc<T>(L.n);
@@ -348,38 +434,45 @@ class Precond final : public PrecondBase {
     std::iota(rperm.begin(), rperm.end(), 0);
     for (size_t k = 0; k < piv.size(); ++k) std::swap(rperm[k], rperm[piv[k]]);
     piv_ = ar_.upload(rperm);
+    const int32_t w_rperm = put(rperm.data(), rperm.size() * sizeof(int32_t));
+    while (img.size() % 4 != 0) img.push_back(0u);
+    for (int l = staged; l + 1 < nl; ++l) {
+      TailLevel<T>& d = td[l - tail_];
+      d.w_wcol = put(h_wcol[l].data(), h_wcol[l].size() * sizeof(int32_t));
+      d.w_wval = put(h_wval[l].data(), h_wval[l].size() * sizeof(T));
+    }
+    if (static_cast<int32_t>(img.size()) != tail_lay_.img_words || w_rperm != tail_lay_.w_rperm)
+      throw Error(CPR_ERR_HIP, "internal: the tail LDS image does not match its layout");
+    tail_img_ = ar_.upload(img);
     // device descriptors of the tail levels, with their LDS vector offsets
-    std::vector<TailLevel<T>> td(nl - tail_);
+    // (x, s0 and s1 of a smoothed level hold the zero entry n as well)
     int32_t off = 0;
     for (int l = tail_; l < nl; ++l) {
       Level& L = lv_[l];
       TailLevel<T>& d = td[l - tail_];
       d.n = L.n;
-      d.off_x = off;
-      d.off_b = off + L.n;
-      off += 2 * L.n;
       if (l == tail_) {
         d.gx = L.x;
         d.gb = L.b;
       }
       if (l + 1 < nl) {
-        d.off_r = off;
-        d.off_s0 = off + L.n;
-        d.off_s1 = off + 2 * L.n;
-        off += 3 * L.n;
-        L.coff_d = ar_.upload(L.coff);
+        d.off_x = off;
+        d.off_b = off + L.n + 1;
+        d.off_r = off + 2 * L.n + 1;
+        d.off_s0 = off + 3 * L.n + 1;
+        d.off_s1 = off + 4 * L.n + 2;
+        off += 5 * L.n + 3;
         d.ncol = static_cast<int32_t>(L.coff.size()) - 1;
-        d.coff = L.coff_d;
-        d.a_rp = L.A.ptr;
         d.a_col = L.A.col;
         d.a_val = L.A.val;
-        d.diag = L.diag;
-        d.p_rp = L.P.ptr;
         d.p_col = L.P.col;
         d.p_val = L.P.val;
-        d.r_rp = L.R.ptr;
         d.r_col = L.R.col;
         d.r_val = L.R.val;
+      } else {
+        d.off_x = off;
+        d.off_b = off + L.n;
+        off += 2 * L.n;
       }
     }
     tail_dev_ = ar_.upload(td);
@@ -498,7 +591,7 @@ class Precond final : public PrecondBase {
     const int nl = static_cast<int>(lv_.size());
     if (l == tail_) {
       if (timer) timer->begin(CPR_KSTAT_TAIL, s);
-      launch_tail_vcycle<T>(tail_dev_, nl - tail_, pre_, post_, nL_, lu_, piv_, tail_lds_, s);
+      launch_tail_vcycle<T>(tail_dev_, nl - tail_, pre_, post_, nL_, lu_, tail_img_, tail_lay_, s);
       if (timer) timer->end(CPR_KSTAT_TAIL, s, tail_bytes_);
       return;
     }
@@ -533,7 +626,8 @@ class Precond final : public PrecondBase {
   Arena ar_;
   std::vector<Level> lv_;
   int tail_ = 0;
-  size_t tail_lds_ = 0;  // dynamic LDS bytes of the tail kernel
+  TailLayout tail_lay_;
+  uint32_t* tail_img_ = nullptr;
   TailLevel<T>* tail_dev_ = nullptr;
   double tail_bytes_ = 0.0;
   int pre_, post_;

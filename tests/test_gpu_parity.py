@@ -132,6 +132,32 @@ def test_vcycle_and_cpr_apply(setup_pair, tail_nnz):
     S_ref.close()
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_tail_with_large_coarsest_level(setup_pair, fp32):
+    """coarse_max 200 leaves a coarsest level of more than 64 rows (117 and
+    192 rows here), which the tail kernel solves with its multi-wavefront
+    substitution instead of the one-wavefront one; the tail (tail_nnz 1e9)
+    and the per-colour path stay bit-identical in both precisions, and the
+    FP64 V-cycle matches the oracle's."""
+    from oracle import amg as amg_oracle
+
+    name, case, A, B, b, S0 = setup_pair
+    S = _solver(case, tail_nnz=10 ** 9, coarse_max=200, precond_fp32=fp32)
+    S_ref = _solver(case, tail_nnz=0, coarse_max=200, precond_fp32=fp32)
+    n_lev = S.level_info(0)["n_levels"]
+    assert S.level_info(n_lev - 1)["n"] > 64
+    rng = np.random.default_rng(17)
+    r = rng.standard_normal(A.n_b)
+    got = S.vcycle(_dev(r)).cpu().numpy()
+    assert np.array_equal(got, S_ref.vcycle(_dev(r)).cpu().numpy())
+    if not fp32:
+        H = cpr.setup(A, amg_oracle.AmgParams(coarse_max=200)).amg
+        want = amg.vcycle(H, r)
+        assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+    S.close()
+    S_ref.close()
+
+
 @pytest.mark.parametrize("layout", [1, 2, 4, 16, 32, 64])
 def test_every_row_layout_bit_identical(setup_pair, layout):
     """Every storage form of the level matrices (1: SELL-64, one lane per row;
