@@ -1,24 +1,26 @@
 // Pressure-AMG kernels: the PGS-SCM colour sweep (Algorithm "PGS-SCM"),
 // residual, restriction and prolongation.
 //
-// Two storage forms, chosen per matrix at SETUP from its row lengths:
-//  * SELL-64, one lane per row (short rows: the finest level, P, R).  Slots
-//    are fetched kUnroll at a time so the gathers of a row overlap.
-//  * Quad-vector CSR (the Galerkin levels): four lanes per row, rows padded
-//    to a multiple of four entries, each lane reading four contiguous entries
-//    per chunk with one vector load (see quad_row_sub); sixteen rows per
-//    wavefront.
-//  * CSR with a group of 16, 32 or 64 lanes per row (long rows of the
-//    Galerkin levels).  Each lane fetches one stored entry of a chunk (4, 8 or
-//    16 chunks in flight, as many as the row needs) and forms its product;
-//    the group then adds the products in stored order.  A 16-lane group is
-//    one DPP row: the running value moves one lane to the right per step
-//    (register moves only, no LDS), so the last lane ends with the sequential
-//    result.  Wider groups broadcast one lane at a time.
-// Either way every row is accumulated exactly as a sequential loop over its
+// Storage forms, chosen per matrix at SETUP from its size and row lengths:
+//  * SELL-64, one lane per row (many short rows: the finest level, P, R).
+//    Slots are fetched U at a time so the gathers of a row overlap.
+//  * Quad-vector CSR (Galerkin levels of medium row length): four lanes per
+//    row, rows padded to a multiple of four entries, each lane reading four
+//    contiguous entries per chunk with one vector load (see quad_row_sub);
+//    sixteen rows per wavefront.
+//  * 16 lanes per row over the same padded CSR data, four contiguous entries
+//    per lane (long rows of the Galerkin levels; see row16v4_sub).
+//  * CSR with a group of 16, 32 or 64 lanes per row, one stored entry per
+//    lane and chunk (selectable; the group adds the products in stored order,
+//    a 16-lane group by DPP moves, wider groups one broadcast at a time).
+// Every form accumulates each row exactly as a sequential loop over its
 // stored entries would (products rounded, then added in order), so results
 // match a sequential implementation bit for bit.  Entries that do not
 // contribute are replaced by a zero product, which leaves the sum unchanged.
+//
+// Rows of a colour are stored in index order and each XCD takes one
+// contiguous range of them (xcd_block), so the rows of a workgroup, and of an
+// XCD, gather mostly the same vector entries.
 #include "kernels_common.hpp"
 
 namespace cpr {
@@ -134,11 +136,8 @@ __global__ __launch_bounds__(kBlock) void k_gs_grp(int32_t lo, int32_t hi, const
                                                    const T* __restrict__ diag, const T* __restrict__ b,
                                                    T* __restrict__ x, const T* __restrict__ s_in,
                                                    T* __restrict__ s_out) {
-  // Rows of a colour are stored longest first, so neighbouring workgroups carry
-  // similar work: the hardware's round-robin of workgroups over the XCDs then
-  // gives every XCD an even share (a contiguous range per XCD would hand one
-  // XCD all the longest rows).  The vectors of these levels fit every L2.
-  const int32_t g = (blockIdx.x * kBlock + threadIdx.x) / G;
+  // each XCD takes one contiguous range of the colour's rows (as k_gs_q4)
+  const int32_t g = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
   const int lane = threadIdx.x % G;
   const int32_t q = lo + g;
   if (q >= hi) return;
@@ -181,16 +180,16 @@ void launch_gs_grp(const MatView<T>& A, const T* diag, int32_t lo, int32_t hi, c
                        b, x, s_in, s_out);
 }
 
-// Quad-vector CSR colour sweep: a quad per row (rows of a colour are stored
-// longest first, so neighbouring workgroups carry similar work and the
-// hardware's round-robin over the XCDs balances them).
+// Quad-vector CSR colour sweep: a quad per row.  Each XCD takes one
+// contiguous range of the colour's rows (rows in index order, so most of the
+// entries its rows gather were written by the same XCD and stay in its L2).
 template <typename T, int CH, bool ZERO>
 __global__ __launch_bounds__(kBlock) void k_gs_q4(int32_t lo, int32_t hi, const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ col, const T* __restrict__ val,
                                                   const T* __restrict__ diag, const T* __restrict__ b,
                                                   T* __restrict__ x, const T* __restrict__ s_in,
                                                   T* __restrict__ s_out) {
-  const int32_t q = lo + (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 2);
+  const int32_t q = lo + (int32_t)((xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) >> 2);
   const int lane = threadIdx.x & 3;
   if (q >= hi) return;
   const T d = diag[q];  // requested with b, off the row's dependent chain
@@ -203,14 +202,18 @@ __global__ __launch_bounds__(kBlock) void k_gs_q4(int32_t lo, int32_t hi, const 
   }
 }
 
-// 16 lanes per row, four contiguous entries per lane (quad-vector CSR data).
+// 16 lanes per row, four contiguous entries per lane (quad-vector CSR data),
+// in workgroups of one wavefront (four rows): a colour's gathers spread over
+// four times as many compute units as with 256-thread workgroups.  Each XCD
+// takes one contiguous range of the colour's rows, as in k_gs_q4.
+constexpr int kV16Block = 64;
 template <typename T, int CH, bool ZERO>
-__global__ __launch_bounds__(kBlock) void k_gs_v16(int32_t lo, int32_t hi, const int32_t* __restrict__ rp,
+__global__ __launch_bounds__(kV16Block) void k_gs_v16(int32_t lo, int32_t hi, const int32_t* __restrict__ rp,
                                                    const int32_t* __restrict__ col, const T* __restrict__ val,
                                                    const T* __restrict__ diag, const T* __restrict__ b,
                                                    T* __restrict__ x, const T* __restrict__ s_in,
                                                    T* __restrict__ s_out) {
-  const int32_t q = lo + (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 4);  // round-robin, as k_gs_grp
+  const int32_t q = lo + (int32_t)((xcd_block(blockIdx.x, gridDim.x) * kV16Block + threadIdx.x) >> 4);
   const int lane = threadIdx.x & 15;
   if (q >= hi) return;
   const T d = diag[q];  // requested with b, off the row's dependent chain
@@ -226,13 +229,13 @@ __global__ __launch_bounds__(kBlock) void k_gs_v16(int32_t lo, int32_t hi, const
 template <typename T, int CH>
 void launch_gs_v16(const MatView<T>& A, const T* diag, int32_t lo, int32_t hi, const T* b, T* x, const T* s_in,
                    T* s_out, bool zero_start, hipStream_t s) {
-  const int grid = div_up((int64_t)(hi - lo) * 16, kBlock);
+  const int grid = div_up((int64_t)(hi - lo) * 16, kV16Block);
   if (zero_start)
-    hipLaunchKernelGGL((k_gs_v16<T, CH, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag, b,
-                       x, s_in, s_out);
-  else
-    hipLaunchKernelGGL((k_gs_v16<T, CH, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag,
+    hipLaunchKernelGGL((k_gs_v16<T, CH, true>), dim3(grid), dim3(kV16Block), 0, s, lo, hi, A.ptr, A.col, A.val, diag,
                        b, x, s_in, s_out);
+  else
+    hipLaunchKernelGGL((k_gs_v16<T, CH, false>), dim3(grid), dim3(kV16Block), 0, s, lo, hi, A.ptr, A.col, A.val,
+                       diag, b, x, s_in, s_out);
 }
 
 template <typename T, int CH>
@@ -351,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_grp(int32_t n, const int32_t* _
                                                      const int32_t* __restrict__ col, const T* __restrict__ val,
                                                      const T* __restrict__ b, const T* __restrict__ x,
                                                      T* __restrict__ y, T* __restrict__ snap, ZeroStart<T> zs) {
-  const int32_t q = (blockIdx.x * kBlock + threadIdx.x) / G;  // round-robin over XCDs, as k_gs_grp
+  const int32_t q = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / G;
   const int lane = threadIdx.x % G;
   if (q >= n) return;
   T acc = (MODE == 0) ? b[q] : (T)0;
@@ -381,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_q4(int32_t n, const int32_t* __
                                                     const int32_t* __restrict__ col, const T* __restrict__ val,
                                                     const T* __restrict__ b, const T* __restrict__ x,
                                                     T* __restrict__ y, T* __restrict__ snap, ZeroStart<T> zs) {
-  const int32_t q = (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 2);
+  const int32_t q = (int32_t)((xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) >> 2);
   const int lane = threadIdx.x & 3;
   if (q >= n) return;
   const T y0 = (MODE == 2) ? y[q] : (T)0;
@@ -399,7 +402,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_v16(int32_t n, const int32_t* _
                                                      const int32_t* __restrict__ col, const T* __restrict__ val,
                                                      const T* __restrict__ b, const T* __restrict__ x,
                                                      T* __restrict__ y, T* __restrict__ snap, ZeroStart<T> zs) {
-  const int32_t q = (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 4);
+  const int32_t q = (int32_t)((xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) >> 4);
   const int lane = threadIdx.x & 15;
   if (q >= n) return;
   const T y0 = (MODE == 2) ? y[q] : (T)0;

@@ -93,21 +93,19 @@ double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
-// Rows of each colour, longest rows first (fewer padded SELL slots), then by
-// index; returns the permutation (device position -> row) and colour offsets.
-void colour_order(int32_t n, const std::vector<int32_t>& ptr, const std::vector<int32_t>& colour, int32_t ncol,
-                  std::vector<int32_t>& perm, std::vector<int32_t>& coff) {
-  perm.resize(n);
-  std::iota(perm.begin(), perm.end(), 0);
-  std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
-    if (colour[a] != colour[b]) return colour[a] < colour[b];
-    const int32_t la = ptr[a + 1] - ptr[a], lb = ptr[b + 1] - ptr[b];
-    if (la != lb) return la > lb;
-    return a < b;
-  });
+// Rows of each colour in index order; returns the permutation (device
+// position -> row) and colour offsets.  Index order keeps rows that are close
+// in the grid close on the device, so the rows a workgroup takes share most
+// of the vector entries they gather (sorting a colour by row length instead
+// scatters them: 10% more solve time at 3.28M DOF).
+void colour_order(int32_t n, const std::vector<int32_t>& colour, int32_t ncol, std::vector<int32_t>& perm,
+                  std::vector<int32_t>& coff) {
   coff.assign(ncol + 1, 0);
   for (int32_t i = 0; i < n; ++i) coff[colour[i] + 1]++;
   for (int32_t c = 0; c < ncol; ++c) coff[c + 1] += coff[c];
+  std::vector<int32_t> next(coff.begin(), coff.end() - 1);
+  perm.resize(n);
+  for (int32_t i = 0; i < n; ++i) perm[next[colour[i]]++] = i;
 }
 
 // Greedy colouring of one level (Algorithm VerticesGrouping) and its device
@@ -117,10 +115,10 @@ struct Colouring {
   int32_t n_colours = 0;
 };
 
-Colouring colour_level(const Pattern& S, const std::vector<int32_t>& ptr) {
+Colouring colour_level(const Pattern& S) {
   Colouring c;
   c.n_colours = vertices_grouping(S, c.colour);
-  colour_order(S.n, ptr, c.colour, c.n_colours, c.perm, c.coff);
+  colour_order(S.n, c.colour, c.n_colours, c.perm, c.coff);
   return c;
 }
 
@@ -196,7 +194,7 @@ void cpr_handle::build_precond() {
       }
       B.ptr[i + 1] = static_cast<int32_t>(B.col.size());
     }
-    return colour_level(B, h_row_ptr);
+    return colour_level(B);
   });
   std::vector<std::future<Colouring>> level_tasks;
   // SETUP phase times (ms), printed to stderr when CPR_SETUP_TRACE is set
@@ -246,8 +244,8 @@ void cpr_handle::build_precond() {
     tp = now_ms();
 
     // colouring of this level (eq. (strong-matrix) pattern) on its own thread
-    level_tasks.push_back(std::async(std::launch::async, [Sc = pattern_from_mask(L.A, L.mask, 2),
-                                                          ptr = L.A.ptr]() { return colour_level(Sc, ptr); }));
+    level_tasks.push_back(
+        std::async(std::launch::async, [Sc = pattern_from_mask(L.A, L.mask, 2)]() { return colour_level(Sc); }));
     const Pattern S = pattern_from_mask(L.A, L.mask, 1);
     const Pattern ST = transpose_pattern(S);
     rs_split(S, ST, L.cf);
