@@ -178,57 +178,83 @@ __device__ __forceinline__ T quad_row_sub(T s, int32_t p0, int32_t p1, ColP col,
   return s;
 }
 
-// The same ordered row sum taken by the 16 lanes of one DPP row over the
-// quad-vector CSR layout: chunk u of a pass covers entries
-// [p + 64u, p + 64u + 64), lane k holds the four entries p + 64u + 4k .. + 3
-// (one vector load each for columns and values).  Lane 0 continues from lane
-// 15's running value (rotate) and subtracts its four products; then, fifteen
-// times, each lane continues from its left neighbour and subtracts its four
-// (lane 0 subtracts zeros), so lane 15 holds the chunk's result, rounded
-// exactly as a sequential loop over the row rounds it.  CH chunks (64 CH
-// entries) are requested at once.
+// One pass of the ordered row sum taken by the 16 lanes of one DPP row over
+// the quad-vector CSR layout: chunk u covers entries [p + 64u, p + 64u + 64),
+// lane k holds the four entries p + 64u + 4k .. + 3 (one vector load each for
+// columns and values).  Lane 0 continues from lane 15's running value
+// (rotate) and subtracts its four products; then, fifteen times, each lane
+// continues from its left neighbour and subtracts its four (lane 0 subtracts
+// zeros), so lane 15 holds the chunk's result, rounded exactly as a
+// sequential loop over the row rounds it.  The CH chunks' loads and gathers
+// are all requested before the first subtraction; chunks past the row's end
+// (u >= nch) read column -1 and value 0 and are not subtracted.
+template <typename T, int CH, typename ColP, typename ValP, typename Prod>
+__device__ __forceinline__ T row16v4_pass(T s, int32_t p, int32_t p1, ColP col, ValP val, int lane, Prod&& prod) {
+  const int nch = min(CH, (p1 - p + 63) / 64);  // uniform across the row group
+  int32_t c[CH][4];
+  T a[CH][4];
+#pragma unroll
+  for (int u = 0; u < CH; ++u) {
+    const int32_t e = p + 64 * u + 4 * lane;
+    if (e < p1) {
+      load4_cols(col, e, c[u]);
+      load4_vals(val, e, a[u]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        c[u][k] = -1;
+        a[u][k] = (T)0;
+      }
+    }
+  }
+  T pr[CH][4];
+#pragma unroll
+  for (int u = 0; u < CH; ++u)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pr[u][k] = prod(c[u][k], a[u][k]);
+#pragma unroll
+  for (int u = 0; u < CH; ++u) {
+    if (u < nch) {
+      T m[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) m[k] = lane == 0 ? (T)0 : pr[u][k];
+      s = dpp_move<kDppRowRor1>(s);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s = s - pr[u][k];
+#pragma unroll
+      for (int step = 1; step < 16; ++step) {
+        s = dpp_move<kDppRowShr1>(s);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s = s - m[k];
+      }
+    }
+  }
+  return s;
+}
+
+// The ordered row sum over passes of up to CH chunks (64 CH entries).  A
+// pass requests only as many chunks as the longest row of the wavefront
+// still needs (1, 2, 4, 6 or 8, a wavefront-uniform choice): a colour kernel
+// lasts as long as its longest row, so CH is sized for the longest rows, and
+// the shorter rows of other wavefronts do not pay for those rows' gathers.
 template <typename T, int CH, typename ColP, typename ValP, typename Prod>
 __device__ __forceinline__ T row16v4_sub(T s, int32_t p0, int32_t p1, ColP col, ValP val, int lane, Prod&& prod) {
   for (int32_t p = p0; p < p1; p += 64 * CH) {
-    const int nch = min(CH, (p1 - p + 63) / 64);  // uniform across the row group
-    int32_t c[CH][4];
-    T a[CH][4];
+    const int need = min(CH, (p1 - p + 63) / 64);
+    int nw = 1;  // chunks the active lanes of the wavefront need
 #pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int32_t e = p + 64 * u + 4 * lane;
-      if (e < p1) {
-        load4_cols(col, e, c[u]);
-        load4_vals(val, e, a[u]);
-      } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          c[u][k] = -1;
-          a[u][k] = (T)0;
-        }
-      }
-    }
-    T pr[CH][4];
-#pragma unroll
-    for (int u = 0; u < CH; ++u)
-#pragma unroll
-      for (int k = 0; k < 4; ++k) pr[u][k] = prod(c[u][k], a[u][k]);
-#pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      if (u < nch) {
-        T m[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) m[k] = lane == 0 ? (T)0 : pr[u][k];
-        s = dpp_move<kDppRowRor1>(s);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) s = s - pr[u][k];
-#pragma unroll
-        for (int step = 1; step < 16; ++step) {
-          s = dpp_move<kDppRowShr1>(s);
-#pragma unroll
-          for (int k = 0; k < 4; ++k) s = s - m[k];
-        }
-      }
-    }
+    for (int k = 1; k < CH; ++k)
+      if (__builtin_amdgcn_ballot_w64(need > k) != 0) nw = k + 1;
+    if (CH <= 1 || nw <= 1)
+      s = row16v4_pass<T, 1>(s, p, p1, col, val, lane, prod);
+    else if (CH <= 2 || nw <= 2)
+      s = row16v4_pass<T, (CH < 2 ? CH : 2)>(s, p, p1, col, val, lane, prod);
+    else if (CH <= 4 || nw <= 4)
+      s = row16v4_pass<T, (CH < 4 ? CH : 4)>(s, p, p1, col, val, lane, prod);
+    else if (CH <= 6 || nw <= 6)
+      s = row16v4_pass<T, (CH < 6 ? CH : 6)>(s, p, p1, col, val, lane, prod);
+    else
+      s = row16v4_pass<T, CH>(s, p, p1, col, val, lane, prod);
   }
   return s;
 }

@@ -83,11 +83,16 @@ int32_t layout_for(int32_t policy, int32_t n, double avg) {
   return avg <= kQuadAvg ? 4 : 2;
 }
 
-// Requests a row keeps in flight: enough that nine rows (or slices) in ten
-// finish in one batch (each further batch costs two dependent memory round
-// trips), no more (the registers held per lane limit the waves in flight).
-// SELL: slots of a slice, 8/16/32; quad-vector CSR: chunks of 16 entries per
-// quad, 2/4/8; 16-lane CSR: chunks of 16 entries, 4/8/16.
+// Requests a row keeps in flight.  SELL and one-entry-per-lane CSR: enough
+// that nine rows (or slices) in ten finish in one batch (each further batch
+// costs two dependent memory round trips), no more (the registers held per
+// lane limit the waves in flight); SELL: slots of a slice, 8/16/32; 16-lane
+// CSR: chunks of 16 entries, 4/8/16.  The quad-vector layouts take every row
+// in one batch up to 128 (quad: chunks of 16 entries, 2/4/8) or 512 entries
+// (16 lanes x 4: chunks of 64, 1/2/4/8): a colour kernel lasts as long as
+// its longest row, and on the Galerkin levels the longest rows are about
+// twice the 90th percentile, so a p90-sized batch would give them a second
+// pass of loads and gathers (1-1.5 us per colour at 3.28M DOF).
 int32_t p90(std::vector<int32_t> v) {
   if (v.empty()) return 0;
   const size_t k = static_cast<size_t>(0.9 * (v.size() - 1));
@@ -97,10 +102,14 @@ int32_t p90(std::vector<int32_t> v) {
 
 int32_t csr_depth(const HostCsr& A, int32_t group) {
   std::vector<int32_t> len(A.n_rows);
-  for (int32_t i = 0; i < A.n_rows; ++i) len[i] = A.ptr[i + 1] - A.ptr[i];
+  int32_t wmax = 0;
+  for (int32_t i = 0; i < A.n_rows; ++i) {
+    len[i] = A.ptr[i + 1] - A.ptr[i];
+    wmax = std::max(wmax, (len[i] + 3) / 4 * 4);  // padded to a multiple of four
+  }
+  if (group == 4) return wmax <= 32 ? 2 : (wmax <= 64 ? 4 : 8);
+  if (group == 2) return wmax <= 64 ? 1 : (wmax <= 128 ? 2 : (wmax <= 256 ? 4 : 8));
   const int32_t w = p90(std::move(len));
-  if (group == 4) return w <= 32 ? 2 : (w <= 64 ? 4 : 8);
-  if (group == 2) return w <= 64 ? 1 : (w <= 128 ? 2 : (w <= 256 ? 4 : 8));
   return w <= 64 ? 4 : (w <= 128 ? 8 : 16);
 }
 
