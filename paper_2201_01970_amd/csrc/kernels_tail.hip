@@ -119,6 +119,15 @@ __device__ __forceinline__ void tail_sweep(const TailLevel<T>& L, T* V, const ui
   cur ^= 1;
 }
 
+// Lane k's value broadcast to the wavefront (k wavefront-uniform): two
+// v_readlane into scalar registers, no LDS round trip.
+__device__ __forceinline__ double lane_value(double v, int k) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffffll), k);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), k);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 template <typename T>
 __global__ __launch_bounds__(kTailThreads) void k_tail_vcycle(const TailLevel<T>* __restrict__ levels, int nlev,
                                                                int pre, int post, int32_t n_coarse,
@@ -199,12 +208,12 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_vcycle(const TailLevel<T>
         const int r = threadIdx.x;
         double xr = r < n ? (double)b[rperm[r]] : 0.0;
         for (int k = 0; k < n; ++k) {
-          const double xk = __shfl(xr, k, kWave);
+          const double xk = lane_value(xr, k);
           if (r > k && r < n) xr = xr - luS[r * n + k] * xk;
         }
         for (int k = n - 1; k >= 0; --k) {
           if (r == k) xr = xr / luS[k * n + k];
-          const double xk = __shfl(xr, k, kWave);
+          const double xk = lane_value(xr, k);
           if (r < k) xr = xr - luS[r * n + k] * xk;
         }
         if (r < n) x[r] = (T)xr;
