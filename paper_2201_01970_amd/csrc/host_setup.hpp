@@ -12,21 +12,50 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
+#include <new>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 namespace cpr {
 
+// Allocator whose resize() leaves new elements uninitialised: the SETUP
+// arrays (hundreds of MB at 3.28M DOF) are written in full by parallel passes
+// right after they are sized, and zero-filling them first cost a serial pass
+// plus every page fault on one thread.
+template <typename T>
+struct NoInitAlloc : std::allocator<T> {
+  template <typename U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <typename U>
+  NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+  template <typename U>
+  void construct(U* p) noexcept(std::is_nothrow_default_constructible<U>::value) {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <typename U, typename... Args>
+  void construct(U* p, Args&&... args) {
+    ::new (static_cast<void*>(p)) U(std::forward<Args>(args)...);
+  }
+};
+template <typename T>
+using HostVec = std::vector<T, NoInitAlloc<T>>;
+
 struct HostCsr {
   int32_t n_rows = 0, n_cols = 0;
-  std::vector<int32_t> ptr, col;
-  std::vector<double> val;
+  HostVec<int32_t> ptr, col;  // resize() leaves entries uninitialised
+  HostVec<double> val;
   int64_t nnz() const { return static_cast<int64_t>(col.size()); }
 };
 
 // Pattern rows (strong neighbours) extracted from a mask over stored entries.
 struct Pattern {
   int32_t n = 0;
-  std::vector<int32_t> ptr, col;
+  HostVec<int32_t> ptr, col;  // resize() leaves entries uninitialised
 };
 
 Pattern pattern_from_mask(const HostCsr& A, const std::vector<uint8_t>& mask, uint8_t bit);

@@ -203,8 +203,8 @@ void cpr_handle::build_precond() {
 
   HostCsr A;
   A.n_rows = A.n_cols = n_b;
-  A.ptr = h_row_ptr;
-  A.col = h_col;
+  A.ptr.assign(h_row_ptr.begin(), h_row_ptr.end());
+  A.col.assign(h_col.begin(), h_col.end());
   A.val.resize(nnz_b);
   for (int32_t k = 0; k < nnz_b; ++k) A.val[k] = h_vals[static_cast<size_t>(k) * 9];
 
