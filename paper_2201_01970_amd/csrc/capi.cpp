@@ -41,7 +41,7 @@ void copy_in(void* dst, const void* src, size_t bytes, int32_t location) {
 }
 
 // Check sizes, ascending columns, range and the diagonal block of every row.
-void validate_pattern(int32_t n, int32_t nnz, const std::vector<int32_t>& rp, const std::vector<int32_t>& col) {
+void validate_pattern(int32_t n, int32_t nnz, const HostVec<int32_t>& rp, const HostVec<int32_t>& col) {
   if (rp[0] != 0 || rp[n] != nnz) throw Error(CPR_ERR_INVALID_ARG, "row_ptr must start at 0 and end at nnz_blocks");
   for (int32_t i = 0; i < n; ++i) {
     if (rp[i + 1] < rp[i]) throw Error(CPR_ERR_INVALID_ARG, "row_ptr is not monotone");
@@ -78,7 +78,7 @@ void build_outer(cpr_handle* h) {
   }
   const int64_t slots = sp[ns];
   std::vector<int32_t> col(static_cast<size_t>(slots) * kWave, kPadCol);
-  std::vector<int64_t> pos(h->nnz_b);
+  HostVec<int64_t> pos(h->nnz_b);  // written in full below
   for (int32_t i = 0; i < n; ++i) {
     const int32_t s = i / kWave, lane = i % kWave;
     int32_t t = sp[s];

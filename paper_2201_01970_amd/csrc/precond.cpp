@@ -267,7 +267,7 @@ class Precond final : public PrecondBase {
 
   Precond(const cpr_params& prm, int32_t n_b, const std::vector<HostLevel>& hl, const std::vector<double>& lu,
           const std::vector<int32_t>& piv, const std::vector<int32_t>& bperm, const std::vector<int32_t>& bcoff,
-          const std::vector<int32_t>& h_row_ptr, const std::vector<int32_t>& h_col,
+          const HostVec<int32_t>& h_row_ptr, const HostVec<int32_t>& h_col,
           const std::vector<int32_t>& bcolour, const double* d_vals_in, hipStream_t s)
       : pre_(prm.pre_sweeps), post_(prm.post_sweeps), n_b_(n_b) {
     const int nl = static_cast<int>(hl.size());
@@ -277,7 +277,7 @@ class Precond final : public PrecondBase {
     // flag on columns of earlier colours), built while the levels are prepared
     struct Stage2Image {
       std::vector<int32_t> sp, col;
-      std::vector<int64_t> pos, diag_pos;
+      HostVec<int64_t> pos, diag_pos;  // written in full below
       std::vector<double> bytes;
     };
     auto stage2_task = std::async(std::launch::async, [&]() {
@@ -501,8 +501,8 @@ class Precond final : public PrecondBase {
     Stage2Image S2 = stage2_task.get();
     std::vector<int32_t>& sp = S2.sp;
     std::vector<int32_t>& col = S2.col;
-    std::vector<int64_t>& pos = S2.pos;
-    std::vector<int64_t>& diag_pos = S2.diag_pos;
+    const auto& pos = S2.pos;
+    const auto& diag_pos = S2.diag_pos;
     stage2_bytes_ = std::move(S2.bytes);
     const int64_t slots = sp.back();
     fine_.n_rows = n;
@@ -656,8 +656,8 @@ class Precond final : public PrecondBase {
 std::unique_ptr<PrecondBase> make_precond(bool fp32, const cpr_params& prm, int32_t n_b,
                                           const std::vector<HostLevel>& hl, const std::vector<double>& lu,
                                           const std::vector<int32_t>& piv, const std::vector<int32_t>& bperm,
-                                          const std::vector<int32_t>& bcoff, const std::vector<int32_t>& h_row_ptr,
-                                          const std::vector<int32_t>& h_col, const std::vector<int32_t>& bcolour,
+                                          const std::vector<int32_t>& bcoff, const HostVec<int32_t>& h_row_ptr,
+                                          const HostVec<int32_t>& h_col, const std::vector<int32_t>& bcolour,
                                           const double* d_vals_in, hipStream_t s) {
   if (fp32)
     return std::make_unique<Precond<float>>(prm, n_b, hl, lu, piv, bperm, bcoff, h_row_ptr, h_col, bcolour,

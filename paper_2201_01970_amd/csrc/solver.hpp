@@ -55,8 +55,8 @@ class Arena {
     bytes_ += static_cast<int64_t>(bytes);
     return static_cast<T*>(p);
   }
-  template <typename T>
-  T* upload(const std::vector<T>& v) {
+  template <typename T, typename Alloc>
+  T* upload(const std::vector<T, Alloc>& v) {
     T* p = alloc<T>(static_cast<int64_t>(v.size()));
     if (!v.empty()) {
       std::lock_guard<std::mutex> lk(device_api_mutex());
@@ -142,7 +142,7 @@ std::unique_ptr<PrecondBase> make_precond(bool fp32, const cpr_params& prm, int3
                                           const std::vector<HostLevel>& hl,
                                           const std::vector<double>& lu, const std::vector<int32_t>& piv,
                                           const std::vector<int32_t>& bperm, const std::vector<int32_t>& bcoff,
-                                          const std::vector<int32_t>& h_row_ptr, const std::vector<int32_t>& h_col,
+                                          const HostVec<int32_t>& h_row_ptr, const HostVec<int32_t>& h_col,
                                           const std::vector<int32_t>& bcolour, const double* d_vals_in,
                                           hipStream_t s);
 
@@ -155,8 +155,8 @@ struct cpr_handle {
   int32_t n_b = 0, nnz_b = 0;
   int32_t *d_rp_pat = nullptr, *d_col_pat = nullptr;  // the input pattern on the device
   int32_t* d_flag = nullptr;                           // pattern comparison result
-  std::vector<int32_t> h_row_ptr, h_col;
-  std::vector<double> h_vals;
+  cpr::HostVec<int32_t> h_row_ptr, h_col;  // resize() leaves entries uninitialised
+  cpr::HostVec<double> h_vals;
   bool h_vals_valid = false;
 
   cpr::Arena fine;  // outer matrix, input values, Krylov workspace
