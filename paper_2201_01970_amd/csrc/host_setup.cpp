@@ -141,6 +141,8 @@ struct RowChunks {
 
 }  // namespace
 
+void parallel_for(int n_chunks, const std::function<void(int, int)>& f) { parallel_chunks(n_chunks, f); }
+
 Pattern pattern_from_mask(const HostCsr& A, const std::vector<uint8_t>& mask, uint8_t bit) {
   Pattern S;
   const int32_t n = A.n_rows;

@@ -12,6 +12,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <memory>
 #include <new>
 #include <type_traits>
@@ -101,5 +102,10 @@ bool dense_lu(int32_t n, std::vector<double>& a, std::vector<int32_t>& piv);
 
 // Host threads used by the row-parallel SETUP steps (at most 16).
 int setup_threads();
+
+// Runs f(chunk, slot) for chunk = 0..n_chunks-1 on the SETUP thread pool
+// (the calling thread takes part); slot < min(setup_threads(), n_chunks)
+// indexes per-call scratch.  Returns when every chunk has finished.
+void parallel_for(int n_chunks, const std::function<void(int, int)>& f);
 
 }  // namespace cpr

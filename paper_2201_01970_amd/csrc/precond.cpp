@@ -3,6 +3,9 @@
 // stage 2 = one forward multi-colour block Gauss-Seidel sweep, fused with the
 // prolongation Pi_P and the residual r = v - A z.
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <future>
 #include <numeric>
@@ -15,18 +18,26 @@ namespace {
 
 // Host SELL-64 image of a CSR matrix with rows in `order` and columns mapped
 // through `colmap`; entries keep their stored order.
+template <typename T>
 struct SellHost {
   int32_t n_rows = 0;
   int32_t uniform = 0;  // width of every slice when all are equal, else 0
-  std::vector<int32_t> slice_ptr, col;
-  std::vector<double> val;
+  HostVec<int32_t> slice_ptr, col;
+  HostVec<T> val;
 };
+
+// Chunks of about `per` items for parallel_for (at most 256).
+int chunks_of(int64_t n, int64_t per) {
+  return static_cast<int>(std::min<int64_t>(256, std::max<int64_t>(1, n / per)));
+}
 
 // When padding every slice to the widest one costs at most 5% more slots, all
 // slices get that width (uniform = the width), which lets the kernels compute
-// a slice's slot range instead of loading it.
-SellHost build_sell(const HostCsr& A, const std::vector<int32_t>& order, const std::vector<int32_t>& colmap) {
-  SellHost S;
+// a slice's slot range instead of loading it.  The slots are filled slice by
+// slice in parallel, padding included (column -1, value 0).
+template <typename T>
+SellHost<T> build_sell(const HostCsr& A, const std::vector<int32_t>& order, const std::vector<int32_t>& colmap) {
+  SellHost<T> S;
   const int32_t n = static_cast<int32_t>(order.size());
   S.n_rows = n;
   const int32_t ns = (n + kWave - 1) / kWave;
@@ -50,17 +61,33 @@ SellHost build_sell(const HostCsr& A, const std::vector<int32_t>& order, const s
   S.slice_ptr.assign(ns + 1, 0);
   for (int32_t s = 0; s < ns; ++s) S.slice_ptr[s + 1] = S.slice_ptr[s] + width[s];
   const int64_t slots = S.slice_ptr[ns];
-  S.col.assign(static_cast<size_t>(slots) * kWave, kPadCol);
-  S.val.assign(static_cast<size_t>(slots) * kWave, 0.0);
-  for (int32_t p = 0; p < n; ++p) {
-    const int32_t i = order[p], s = p / kWave, lane = p % kWave;
-    int32_t t = S.slice_ptr[s];
-    for (int32_t q = A.ptr[i]; q < A.ptr[i + 1]; ++q, ++t) {
-      const size_t e = static_cast<size_t>(t) * kWave + lane;
-      S.col[e] = colmap.empty() ? A.col[q] : colmap[A.col[q]];
-      S.val[e] = A.val[q];
-    }
-  }
+  S.col.resize(static_cast<size_t>(slots) * kWave);
+  S.val.resize(static_cast<size_t>(slots) * kWave);
+  const int nch = chunks_of(ns, 64);
+  parallel_for(nch, [&](int ch, int) {
+    const int32_t s0 = static_cast<int32_t>(static_cast<int64_t>(ns) * ch / nch);
+    const int32_t s1 = static_cast<int32_t>(static_cast<int64_t>(ns) * (ch + 1) / nch);
+    for (int32_t s = s0; s < s1; ++s)
+      for (int32_t lane = 0; lane < kWave; ++lane) {
+        const int32_t p = s * kWave + lane;
+        int32_t q = 0, q1 = 0;
+        if (p < n) {
+          q = A.ptr[order[p]];
+          q1 = A.ptr[order[p] + 1];
+        }
+        for (int32_t t = S.slice_ptr[s]; t < S.slice_ptr[s + 1]; ++t) {
+          const size_t e = static_cast<size_t>(t) * kWave + lane;
+          if (q < q1) {
+            S.col[e] = colmap.empty() ? A.col[q] : colmap[A.col[q]];
+            S.val[e] = static_cast<T>(A.val[q]);
+            ++q;
+          } else {
+            S.col[e] = kPadCol;
+            S.val[e] = static_cast<T>(0);
+          }
+        }
+      }
+  });
   return S;
 }
 
@@ -113,7 +140,7 @@ int32_t csr_depth(const HostCsr& A, int32_t group) {
   return w <= 64 ? 4 : (w <= 128 ? 8 : 16);
 }
 
-int32_t sell_depth(const std::vector<int32_t>& slice_ptr) {
+int32_t sell_depth(const HostVec<int32_t>& slice_ptr) {
   std::vector<int32_t> width(slice_ptr.size() > 0 ? slice_ptr.size() - 1 : 0);
   for (size_t s = 0; s < width.size(); ++s) width[s] = slice_ptr[s + 1] - slice_ptr[s];
   const int32_t w = p90(std::move(width));
@@ -138,8 +165,8 @@ struct DevMat {
 template <typename T>
 struct HostMat {
   int32_t n_rows = 0, group = 1, depth = 8, width = 0;
-  std::vector<int32_t> ptr, col;
-  std::vector<T> val;
+  HostVec<int32_t> ptr, col;
+  HostVec<T> val;
 };
 
 template <typename T>
@@ -152,33 +179,43 @@ HostMat<T> build_mat(const HostCsr& A, const std::vector<int32_t>& order, const 
   int32_t layout = layout_for(policy, n, avg);
   if (force_csr) layout = 4;
   if (layout == 1) {
-    SellHost S = build_sell(A, order, colmap);
+    SellHost<T> S = build_sell<T>(A, order, colmap);
     M.group = 1;
     M.depth = sell_depth(S.slice_ptr);
     M.width = S.uniform;
     M.ptr = std::move(S.slice_ptr);
     M.col = std::move(S.col);
-    M.val.assign(S.val.begin(), S.val.end());
+    M.val = std::move(S.val);
     return M;
   }
   // Quad-vector CSR pads every row to a multiple of four entries (column -1,
   // value 0), so each row starts on a 16-byte boundary of the column array.
+  // Row offsets first, then the rows filled in parallel.
   const int32_t pad = (layout == 4 || layout == 2) ? 4 : 1;
   M.ptr.assign(n + 1, 0);
-  M.col.reserve(A.nnz() + (pad - 1) * static_cast<size_t>(n));
-  M.val.reserve(A.nnz() + (pad - 1) * static_cast<size_t>(n));
   for (int32_t p = 0; p < n; ++p) {
     const int32_t i = order[p];
-    for (int32_t q = A.ptr[i]; q < A.ptr[i + 1]; ++q) {
-      M.col.push_back(colmap.empty() ? A.col[q] : colmap[A.col[q]]);
-      M.val.push_back(static_cast<T>(A.val[q]));
-    }
-    while (M.col.size() % pad != 0) {
-      M.col.push_back(kPadCol);
-      M.val.push_back(static_cast<T>(0));
-    }
-    M.ptr[p + 1] = static_cast<int32_t>(M.col.size());
+    M.ptr[p + 1] = M.ptr[p] + (A.ptr[i + 1] - A.ptr[i] + pad - 1) / pad * pad;
   }
+  M.col.resize(M.ptr[n]);
+  M.val.resize(M.ptr[n]);
+  const int nch = chunks_of(n, 2048);
+  parallel_for(nch, [&](int ch, int) {
+    const int32_t p0 = static_cast<int32_t>(static_cast<int64_t>(n) * ch / nch);
+    const int32_t p1 = static_cast<int32_t>(static_cast<int64_t>(n) * (ch + 1) / nch);
+    for (int32_t p = p0; p < p1; ++p) {
+      const int32_t i = order[p];
+      int32_t e = M.ptr[p];
+      for (int32_t q = A.ptr[i]; q < A.ptr[i + 1]; ++q, ++e) {
+        M.col[e] = colmap.empty() ? A.col[q] : colmap[A.col[q]];
+        M.val[e] = static_cast<T>(A.val[q]);
+      }
+      for (; e < M.ptr[p + 1]; ++e) {
+        M.col[e] = kPadCol;
+        M.val[e] = static_cast<T>(0);
+      }
+    }
+  });
   M.group = layout;
   M.depth = csr_depth(A, layout);
   return M;
@@ -339,6 +376,12 @@ class Precond final : public PrecondBase {
       int64_t nnz_p = 0, nnz_r = 0;
       std::vector<double> colour_bytes;
     };
+    // phase times (ms), printed to stderr when CPR_SETUP_TRACE is set
+    auto clock_ms = []() {
+      return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+    };
+    const double t_start = clock_ms();
+    double t_wait = 0.0;
     std::vector<std::future<LevelImage>> images;
     for (int l = 0; l + 1 < nl; ++l)
       images.push_back(std::async(std::launch::async, [&, l]() {
@@ -348,13 +391,17 @@ class Precond final : public PrecondBase {
         const int32_t n = H.A.n_rows;
         I.A = build_mat<T>(H.A, H.perm, inv[l], prm.row_layout, in_tail);
         I.diag.resize(n);
-        for (int32_t p = 0; p < n; ++p) {
-          const int32_t i = H.perm[p];
-          double d = 0.0;
-          for (int32_t q = H.A.ptr[i]; q < H.A.ptr[i + 1]; ++q)
-            if (H.A.col[q] == i) d = H.A.val[q];
-          I.diag[p] = static_cast<T>(d);
-        }
+        const int nch = chunks_of(n, 4096);
+        parallel_for(nch, [&](int ch, int) {
+          const int32_t p1 = static_cast<int32_t>(static_cast<int64_t>(n) * (ch + 1) / nch);
+          for (int32_t p = static_cast<int32_t>(static_cast<int64_t>(n) * ch / nch); p < p1; ++p) {
+            const int32_t i = H.perm[p];
+            double d = 0.0;
+            for (int32_t q = H.A.ptr[i]; q < H.A.ptr[i + 1]; ++q)
+              if (H.A.col[q] == i) d = H.A.val[q];
+            I.diag[p] = static_cast<T>(d);
+          }
+        });
         I.P = build_mat<T>(H.P, H.perm, inv[l + 1], prm.row_layout, in_tail);
         const HostCsr R = transpose(H.P);
         I.R = build_mat<T>(R, hl[l + 1].perm, inv[l], prm.row_layout, in_tail);
@@ -398,7 +445,9 @@ class Precond final : public PrecondBase {
       L.x = ar_.alloc<T>(L.n);
       L.b = ar_.alloc<T>(L.n);
       if (l + 1 < nl) {
+        const double tw = clock_ms();
         LevelImage I = images[l].get();
+        t_wait += clock_ms() - tw;
         if (l >= tail_) {
           // the sweep matrix of the tail: diagonal and padding point at the
           // zero entry n with value 0
@@ -494,11 +543,13 @@ class Precond final : public PrecondBase {
     }
     tail_bytes_ += 8.0 * nL_ * nL_;
 
+    const double t_levels = clock_ms();
     // ---- fine level for stage 2: cells in block-colour order
     bcoff_ = bcoff;
     cell_ = ar_.upload(bperm);
     const int32_t n = n_b;
     Stage2Image S2 = stage2_task.get();
+    const double t_s2wait = clock_ms();
     std::vector<int32_t>& sp = S2.sp;
     std::vector<int32_t>& col = S2.col;
     const auto& pos = S2.pos;
@@ -524,6 +575,11 @@ class Precond final : public PrecondBase {
     HIPCHK(hipStreamSynchronize(s));
     if (sing) throw Error(CPR_ERR_SINGULAR_BLOCK, "a 3x3 diagonal block is singular");
     pe_ = ar_.alloc<T>(n);
+    if (std::getenv("CPR_SETUP_TRACE"))
+      std::fprintf(stderr,
+                   "[cpr setup] device images: levels %.1f ms (waiting for host images %.1f), stage-2 image wait "
+                   "%.1f, stage 2 upload and D^-1 %.1f\n",
+                   t_levels - t_start, t_wait, t_s2wait - t_levels, clock_ms() - t_s2wait);
   }
 
   void apply(const double* v, void* zv, hipStream_t s) override {
