@@ -1,6 +1,9 @@
 // extern "C" entry points: argument checks, exception-to-status translation.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -77,17 +80,28 @@ void build_outer(cpr_handle* h) {
     sp[s + 1] = sp[s] + w;
   }
   const int64_t slots = sp[ns];
-  std::vector<int32_t> col(static_cast<size_t>(slots) * kWave, kPadCol);
-  HostVec<int64_t> pos(h->nnz_b);  // written in full below
-  for (int32_t i = 0; i < n; ++i) {
-    const int32_t s = i / kWave, lane = i % kWave;
-    int32_t t = sp[s];
-    for (int32_t k = h->h_row_ptr[i]; k < h->h_row_ptr[i + 1]; ++k, ++t) {
-      const size_t e = static_cast<size_t>(t) * kWave + lane;
-      col[e] = h->h_col[k];
-      pos[k] = static_cast<int64_t>(e);
-    }
-  }
+  HostVec<int32_t> col(static_cast<size_t>(slots) * kWave);  // written in full below
+  HostVec<int64_t> pos(h->nnz_b);
+  const int nch = static_cast<int>(std::min<int64_t>(256, std::max<int64_t>(1, ns / 64)));
+  parallel_for(nch, [&](int ch, int) {
+    const int32_t s1 = static_cast<int32_t>(static_cast<int64_t>(ns) * (ch + 1) / nch);
+    for (int32_t s = static_cast<int32_t>(static_cast<int64_t>(ns) * ch / nch); s < s1; ++s)
+      for (int32_t lane = 0; lane < kWave; ++lane) {
+        const int32_t i = s * kWave + lane;
+        int32_t k = i < n ? h->h_row_ptr[i] : 0;
+        const int32_t k1 = i < n ? h->h_row_ptr[i + 1] : 0;
+        for (int32_t t = sp[s]; t < sp[s + 1]; ++t) {
+          const size_t e = static_cast<size_t>(t) * kWave + lane;
+          if (k < k1) {
+            col[e] = h->h_col[k];
+            pos[k] = static_cast<int64_t>(e);
+            ++k;
+          } else {
+            col[e] = kPadCol;
+          }
+        }
+      }
+  });
   h->outer.n_rows = n;
   h->outer.slots = slots;
   h->outer.slice_ptr = h->fine.upload(sp);
@@ -165,6 +179,11 @@ cpr_status cpr_setup(const cpr_bsr* A, const cpr_params* p, void* hip_stream, cp
     h->stream = static_cast<hipStream_t>(hip_stream);  // NULL = the default stream
     h->n_b = A->n_block_rows;
     h->nnz_b = A->nnz_blocks;
+    // phase times (ms), printed to stderr when CPR_SETUP_TRACE is set
+    auto clock_ms = []() {
+      return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+    };
+    const double t0 = clock_ms();
     h->h_row_ptr.resize(h->n_b + 1);
     h->h_col.resize(h->nnz_b);
     copy_in(h->h_row_ptr.data(), A->row_ptr, (h->n_b + 1) * sizeof(int32_t), A->location);
@@ -173,14 +192,26 @@ cpr_status cpr_setup(const cpr_bsr* A, const cpr_params* p, void* hip_stream, cp
     h->d_rp_pat = h->fine.upload(h->h_row_ptr);
     h->d_col_pat = h->fine.upload(h->h_col);
     h->d_flag = h->fine.alloc<int32_t>(1);
-    h->h_vals.resize(static_cast<size_t>(h->nnz_b) * 9);
-    copy_in(h->h_vals.data(), A->values, h->h_vals.size() * sizeof(double), A->location);
-    h->h_vals_valid = true;
-    h->d_vals_in = h->fine.upload(h->h_vals);
+    // the values go straight to the handle's device copy (SETUP reads what it
+    // needs of them on the device)
+    h->d_vals_in = h->fine.alloc<double>(static_cast<int64_t>(h->nnz_b) * 9);
+    {
+      std::lock_guard<std::mutex> lk(device_api_mutex());
+      HIPCHK(hipMemcpy(h->d_vals_in, A->values, static_cast<size_t>(h->nnz_b) * 9 * sizeof(double),
+                       A->location == CPR_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+    }
+    const double t1 = clock_ms();
     build_outer(h);
     launch_bsr_values_to_sell<double>(h->nnz_b, h->d_vals_in, h->d_pos_outer, h->outer.val, h->stream);
+    const double t2 = clock_ms();
     alloc_krylov(h);
+    const double t3 = clock_ms();
     h->build_precond();
+    if (std::getenv("CPR_SETUP_TRACE"))
+      std::fprintf(stderr,
+                   "[cpr setup] input copy, checks and upload %.1f ms, outer SpMV image %.1f, Krylov memory %.1f, "
+                   "preconditioner %.1f\n",
+                   t1 - t0, t2 - t1, t3 - t2, clock_ms() - t3);
     return CPR_OK;
   });
   if (st != CPR_OK) {
@@ -215,14 +246,9 @@ cpr_status cpr_update_values(cpr_handle* h, const cpr_bsr* A) {
     }
     if (!same) throw Error(CPR_ERR_PATTERN_MISMATCH, "sparsity pattern differs from the handle's");
     const size_t bytes = static_cast<size_t>(h->nnz_b) * 9 * sizeof(double);
-    if (A->location == CPR_MEM_DEVICE) {
-      HIPCHK(hipMemcpyAsync(h->d_vals_in, A->values, bytes, hipMemcpyDeviceToDevice, h->stream));
-      h->h_vals_valid = false;
-    } else {
-      std::memcpy(h->h_vals.data(), A->values, bytes);
-      h->h_vals_valid = true;
-      HIPCHK(hipMemcpyAsync(h->d_vals_in, h->h_vals.data(), bytes, hipMemcpyHostToDevice, h->stream));
-    }
+    HIPCHK(hipMemcpyAsync(h->d_vals_in, A->values, bytes,
+                          A->location == CPR_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          h->stream));
     launch_bsr_values_to_sell<double>(h->nnz_b, h->d_vals_in, h->d_pos_outer, h->outer.val, h->stream);
     HIPCHK(hipStreamSynchronize(h->stream));
     h->values_changed = true;

@@ -99,6 +99,13 @@ template <typename T>
 void launch_block_inverse(int32_t n, const double* vals, const int64_t* diag_pos, T* dinv, int32_t ld,
                           int32_t* singular, hipStream_t s);
 
+// For SETUP, from the input BSR (row pointers, columns, values on the device):
+// pval[k] = entry (0,0) of block k; nonzero[k] = 1 if block k has a nonzero
+// entry; *bad_row = min(*bad_row, i) for every row i whose diagonal block fails
+// LU with partial pivoting (pivot <= 1e-300 * max |block entry|).
+void launch_setup_values(int32_t n, const int32_t* rp, const int32_t* col, const double* vals, double* pval,
+                         uint8_t* nonzero, int32_t* bad_row, hipStream_t s);
+
 // Scatter BSR values (row-major blocks in input order) into a block SELL layout
 // given slot positions pos[k] (slot index of input block k, lane included).
 template <typename T>

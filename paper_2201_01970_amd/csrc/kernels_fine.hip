@@ -275,6 +275,58 @@ __global__ __launch_bounds__(kBlock) void k_block_inverse(int32_t n, const doubl
   }
 }
 
+// SETUP's view of the input values, one thread per block row i (rows and
+// columns of the input BSR): the pressure entry (0,0) of every stored block,
+// whether the block has any nonzero entry (stage-2 block graph), and the
+// first row whose diagonal block fails LU with partial pivoting (a pivot not
+// above 1e-300 times the block's largest entry, or an all-zero block).
+__global__ __launch_bounds__(kBlock) void k_setup_values(int32_t n, const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ col,
+                                                         const double* __restrict__ vals, double* __restrict__ pval,
+                                                         uint8_t* __restrict__ nonzero, int32_t* __restrict__ bad_row) {
+  const int32_t i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+    const double* v = vals + (int64_t)k * 9;
+    pval[k] = v[0];
+    bool nz = false;
+    for (int e = 0; e < 9; ++e) nz = nz || v[e] != 0.0;
+    nonzero[k] = nz ? 1 : 0;
+    if (col[k] != i) continue;
+    double a[3][3], amax = 0.0;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        a[r][c] = v[3 * r + c];
+        amax = fmax(amax, fabs(a[r][c]));
+      }
+    bool bad = !(amax > 0.0);
+    for (int kk = 0; kk < 3 && !bad; ++kk) {
+      int p = kk;
+      for (int r = kk + 1; r < 3; ++r)
+        if (fabs(a[r][kk]) > fabs(a[p][kk])) p = r;
+      if (!(fabs(a[p][kk]) > 1e-300 * amax)) bad = true;
+      for (int c = 0; c < 3; ++c) {
+        const double t = a[kk][c];
+        a[kk][c] = a[p][c];
+        a[p][c] = t;
+      }
+      for (int r = kk + 1; r < 3 && !bad; ++r) {
+        const double l = a[r][kk] / a[kk][kk];
+        for (int c = kk + 1; c < 3; ++c) a[r][c] = a[r][c] - l * a[kk][c];
+      }
+    }
+    if (bad) atomicMin(bad_row, i);
+  }
+}
+
+void launch_setup_values(int32_t n, const int32_t* rp, const int32_t* col, const double* vals, double* pval,
+                         uint8_t* nonzero, int32_t* bad_row, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_setup_values, dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, rp, col, vals, pval, nonzero,
+                     bad_row);
+  CPR_LAUNCH_CHECK();
+}
+
 template <typename T>
 void launch_block_inverse(int32_t n, const double* vals, const int64_t* diag_pos, T* dinv, int32_t ld,
                           int32_t* singular, hipStream_t s) {

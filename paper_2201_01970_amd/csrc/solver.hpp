@@ -156,8 +156,6 @@ struct cpr_handle {
   int32_t *d_rp_pat = nullptr, *d_col_pat = nullptr;  // the input pattern on the device
   int32_t* d_flag = nullptr;                           // pattern comparison result
   cpr::HostVec<int32_t> h_row_ptr, h_col;  // resize() leaves entries uninitialised
-  cpr::HostVec<double> h_vals;
-  bool h_vals_valid = false;
 
   cpr::Arena fine;  // outer matrix, input values, Krylov workspace
   cpr::DevSell<double> outer;
