@@ -108,7 +108,8 @@ def serve_bench(args):
     first requests (all submitted at once) fixes the service rate; the timed
     pass submits every request at Poisson arrival times with rate
     lambda = 0.8 x saturated throughput and reports p50/p99 latency from
-    arrival to completion and the completed solves per second.
+    arrival to completion and the completed solves per second.  Requests are
+    generated before both passes.
     """
     import multiprocessing as mp
     import threading
@@ -128,9 +129,9 @@ def serve_bench(args):
     params = Params(precond_fp32=True)
     budget = int(args.budget_gb * (1 << 30))
 
-    def run_pass(sub_descs, rate):
+    def run_pass(sub_descs, rate, pregenerated=None):
         srv = Server(budget, args.slots, params)
-        it = pool.imap(_gen_request, sub_descs, chunksize=1)
+        it = pregenerated if pregenerated is not None else pool.imap(_gen_request, sub_descs, chunksize=1)
         rng = np.random.default_rng(1301)
         t0 = time.perf_counter()
         arrivals = []
@@ -178,13 +179,22 @@ def serve_bench(args):
         srv.close()
         return results, arrivals, wall, stats
 
+    # every request is generated before the passes (≈ 65 GB of host memory for
+    # the 512-request stream), so that both measure the server, not the
+    # request generator (12 processes make ≈ 5.6 requests/s, a third of the
+    # server's saturated rate)
+    reqs = []
+    for k, r in enumerate(pool.imap(_gen_request, descs, chunksize=1)):
+        reqs.append(r)
+        if (k + 1) % 64 == 0:
+            print(f"[serve] generated {k + 1}/{len(descs)} requests", file=sys.stderr, flush=True)
     n_sat = min(args.saturation_requests, len(descs))
-    res_sat, _, wall_sat, _ = run_pass(descs[:n_sat], None)
+    res_sat, _, wall_sat, _ = run_pass(descs[:n_sat], None, reqs[:n_sat])
     sat_rate = n_sat / wall_sat
     rate = args.rate if args.rate else 0.8 * sat_rate
     print(f"[serve] saturation: {n_sat} requests in {wall_sat:.1f}s = {sat_rate:.2f}/s; lambda = {rate:.2f}/s",
           file=sys.stderr, flush=True)
-    res, arrivals, wall, stats = run_pass(descs, rate)
+    res, arrivals, wall, stats = run_pass(descs, rate, reqs)
     pool.close()
     lat = [info["latency_ms"] for info, _ in res.values()]
     ok = [info for info, _ in res.values() if info["status"] == "CPR_OK"]
@@ -195,6 +205,7 @@ def serve_bench(args):
         "value": _pct(lat, 0.5), "unit": "ms", "higher_is_better": False,
         "p50_ms": _pct(lat, 0.5), "p90_ms": _pct(lat, 0.9), "p99_ms": _pct(lat, 0.99),
         "solves_per_s": len(ok) / wall, "lambda_per_s": rate, "saturated_per_s": sat_rate,
+        "arrivals_per_s": (len(arrivals) - 1) / (arrivals[-1] - arrivals[0]) if len(arrivals) > 1 else None,
         "requests": len(descs), "completed_ok": len(ok), "wall_s": wall,
         "iterations_median": _pct(its, 0.5), "relres_true_max": max(rel) if rel else None,
         "rebuilt": sum(1 for info in ok if info["rebuilt"]),
