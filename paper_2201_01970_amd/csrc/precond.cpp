@@ -100,14 +100,19 @@ SellHost<T> build_sell(const HostCsr& A, const std::vector<int32_t>& order, cons
 // wins on the finest levels (about 7 and 15 entries per row) and on P and R at
 // scale, 16-lane groups win on every Galerkin level with 30-90 entries per row
 // (about 2x faster than 32- or 64-lane groups) and on all small matrices.
+// Quad-vector rows (four lanes, 16 entries per chunk, sixteen rows per
+// wavefront) win over 16-lane rows while rows average at most 24 entries or
+// all fit two quad chunks (32 entries: a 16-lane chunk of 64 would leave most
+// lanes idle).
 constexpr int32_t kSellRows = 32768;
 constexpr double kSellAvg = 10.0;
 constexpr double kQuadAvg = 24.0;
+constexpr int32_t kQuadMax = 32;
 
-int32_t layout_for(int32_t policy, int32_t n, double avg) {
+int32_t layout_for(int32_t policy, int32_t n, double avg, int32_t max_len) {
   if (policy != 0) return policy;
   if (n >= kSellRows && avg <= kSellAvg) return 1;
-  return avg <= kQuadAvg ? 4 : 2;
+  return (avg <= kQuadAvg || max_len <= kQuadMax) ? 4 : 2;
 }
 
 // Requests a row keeps in flight.  SELL and one-entry-per-lane CSR: enough
@@ -176,7 +181,9 @@ HostMat<T> build_mat(const HostCsr& A, const std::vector<int32_t>& order, const 
   const int32_t n = static_cast<int32_t>(order.size());
   M.n_rows = n;
   const double avg = n > 0 ? static_cast<double>(A.nnz()) / n : 0.0;
-  int32_t layout = layout_for(policy, n, avg);
+  int32_t max_len = 0;
+  for (int32_t i = 0; i < A.n_rows; ++i) max_len = std::max(max_len, A.ptr[i + 1] - A.ptr[i]);
+  int32_t layout = layout_for(policy, n, avg, max_len);
   if (force_csr) layout = 4;
   if (layout == 1) {
     SellHost<T> S = build_sell<T>(A, order, colmap);
