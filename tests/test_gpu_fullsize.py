@@ -5,6 +5,10 @@ configuration the benchmark times, checked where the oracle can follow:
   the oracle's ordered sum (bit for bit);
 * the GPU strength masks of level 0 on sampled rows against the oracle's
   definitions (bit for bit);
+* one PGS-SCM sweep on each of levels 0-3 on sampled rows: each sampled row
+  is recomputed by the oracle's colour sweep from the values the sweep saw
+  when its colour started (the GPU's output on earlier colours, the start
+  values elsewhere), bit for bit;
 * properties that hold at any size: the level-0 colouring is a partition into
   classes independent in S and S^T; every F point with strong dependencies
   has a strong C dependency; level sizes shrink;
@@ -94,6 +98,41 @@ def test_fullsize_spmv_sampled_rows(big):
     info = S.level_info(0)
     sizes = [S.level_info(l)["n"] for l in range(info["n_levels"])]
     assert all(a > b for a, b in zip(sizes, sizes[1:])) and sizes[-1] <= 50
+    S.close()
+
+
+def test_fullsize_sweeps_sampled_rows(big):
+    """One sweep of Alg. PGS-SCM updates colour k from a snapshot holding the
+    new values of colours < k and the old values elsewhere, so the GPU output
+    of a sampled row of colour k is fixed by that snapshot alone."""
+    from oracle import amg
+    from paper_2201_01970_amd import Params, Solver
+
+    case, b = big
+    S = Solver(_dev(case.row_ptr), _dev(case.col), _dev(case.vals.reshape(-1)), Params())
+    rng = np.random.default_rng(31)
+    for l in range(4):
+        lv = S.level_arrays(l)
+        n = lv["row_ptr"].size - 1
+        A = Csr(n, n, lv["row_ptr"].astype(np.int64), lv["col"].astype(np.int64), lv["val"])
+        colour = lv["colour"]
+        rows = _sample_rows(n, 4000, 40 + l)
+        diag = np.zeros(n)
+        for i in rows:
+            c, v = A.row(i)
+            diag[i] = v[c == i][0]
+        bb = rng.standard_normal(n)
+        for zero_start in ((False, True) if l == 0 else (False,)):
+            x0 = np.zeros(n) if zero_start else rng.standard_normal(n)
+            got = S.smooth(l, _dev(x0.copy()), _dev(bb), sweeps=1, zero_start=zero_start).cpu().numpy()
+            for k in range(int(colour.max()) + 1):
+                rk = rows[colour[rows] == k]
+                if rk.size == 0:
+                    continue
+                snap = np.where(colour < k, got, x0)
+                amg.colour_sweep(A, [rk], snap, bb, diag)
+                assert np.array_equal(snap[rk], got[rk]), (l, k, zero_start)
+            print(f"[fullsize] level {l} n={n} sweep on {rows.size} sampled rows bit-exact", flush=True)
     S.close()
 
 
