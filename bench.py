@@ -367,7 +367,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solve of one Jacobian is not "
-              "sharded across GPUs in this build", file=sys.stderr)
+              "sharded across GPUs by this library", file=sys.stderr)
         sys.exit(2)
     if args.serve:
         serve_bench(args)

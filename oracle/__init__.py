@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and
 its Python binding) imports, calls or links anything here; only the tests,
-the graft smoke check and the benchmark's CPU-baseline leg do.  It shares no
+the package's smoke check and the benchmark's CPU-baseline leg do.  It shares no
 code with the HIP path: the two meet only at the seeded input generator in
 ``workloads/``, which holds none of the method's arithmetic.
 

@@ -8,7 +8,7 @@ Notation (Section 5.2): S_i is the set of j with S_ij = 1 (row i of the strong
 matrix); |S_i| is the influence of vertex i; the "second circle" of i is the
 union of S_k over k in S_i, minus S_i and i itself.
 
-Readings where the printed algorithm is ambiguous (each listed in the design doc):
+Readings where the printed algorithm is ambiguous:
 
 * selection: the vertex of largest influence |S_i|, ties broken by the
   smallest vertex index; the influence is the static row count of S;

@@ -3,7 +3,7 @@
 Follows Algorithm "ASCPR-GMRES" of Section 4 (restarted GMRES, classical
 Gram-Schmidt Arnoldi, happy breakdown when h_{j+1,j} = 0, least-squares
 problem on the Hessenberg matrix, true residual at every restart) with these
-readings, each listed in the design doc:
+readings:
 
 * flexible form: z_j = B p_j is stored and the update is x = x0 + Z y (with a
   fixed linear B this is the same iterate as the printed x0 + B(P_m y));

@@ -6,8 +6,7 @@ property data used in the paper's experiments (Section 6) is not available, so
 the workloads below stand in for it with the same grid shape (60x220x85),
 strong layered heterogeneity, inactive cells and channelised permeability.
 
-Value rules (one reading of an under-determined recipe; every choice is listed
-in DESIGN.md under "input recipe"):
+Value rules (one reading of an under-determined recipe):
 
 * cells are ordered naturally, c = i + nx*(j + ny*k); inactive cells are
   skipped and the active ones renumbered in the same order; the unknowns of a
