@@ -47,6 +47,11 @@ def _torch():
     return torch
 
 
+def _host(arr):
+    """A numpy view (or host copy) of a numpy array or torch tensor."""
+    return arr if isinstance(arr, np.ndarray) else arr.detach().cpu().numpy()
+
+
 def _ptr(arr):
     """Address of a contiguous numpy array or torch tensor."""
     if isinstance(arr, np.ndarray):
@@ -76,18 +81,18 @@ class Solver:
 
     def _as_bsr(self, row_ptr, col, vals):
         torch = _torch()
+        # one memory location covers the three arrays: the pattern follows the values
         if isinstance(vals, np.ndarray):
-            rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
-            cl = np.ascontiguousarray(col, dtype=np.int32)
+            rp = np.ascontiguousarray(_host(row_ptr), dtype=np.int32)
+            cl = np.ascontiguousarray(_host(col), dtype=np.int32)
             vv = np.ascontiguousarray(vals, dtype=np.float64).reshape(-1)
             loc = A.CPR_MEM_HOST
         else:
-            rp = row_ptr.to(dtype=torch.int32).contiguous()
-            cl = col.to(dtype=torch.int32).contiguous()
+            rp = torch.as_tensor(row_ptr).to(dtype=torch.int32).contiguous()
+            cl = torch.as_tensor(col).to(dtype=torch.int32).contiguous()
             vv = vals.to(dtype=torch.float64).contiguous().reshape(-1)
             loc = A.CPR_MEM_DEVICE if vv.is_cuda else A.CPR_MEM_HOST
-            if loc == A.CPR_MEM_DEVICE:
-                rp, cl = rp.to(vv.device), cl.to(vv.device)
+            rp, cl = rp.to(vv.device), cl.to(vv.device)
         n = int(rp.shape[0]) - 1
         nnz = int(cl.shape[0])
         self._bsr = A.cpr_bsr(n, nnz, 3, _ptr(rp), _ptr(cl), _ptr(vv), loc)

@@ -64,6 +64,34 @@ def test_sequence_matches_oracle(sequence, rule, fp32):
     S.close()
 
 
+def test_values_from_host_or_device_agree(sequence):
+    """cpr_setup and cpr_update_values take the matrix from host or device
+    memory; a handle fed from the host (numpy, or a CPU tensor), one fed from
+    the device, and one set up on the device and updated from the host give
+    the same rebuild decisions, iteration counts and iterates bit for bit."""
+    from paper_2201_01970_amd import Params, Solver
+
+    c0 = sequence[0][0]
+    p = Params(reuse_mode=1, mu=6)
+    S_dev = Solver(_dev(c0.row_ptr), _dev(c0.col), _dev(c0.vals.reshape(-1)), p)
+    S_host = Solver(c0.row_ptr, c0.col, c0.vals.reshape(-1), p)
+    S_mix = Solver(_dev(c0.row_ptr), _dev(c0.col), _dev(c0.vals.reshape(-1)), p)
+    for k, (case, b) in enumerate(sequence):
+        if k > 0:
+            S_dev.update_values(_dev(case.vals.reshape(-1)))
+            S_host.update_values(np.ascontiguousarray(case.vals.reshape(-1)))
+            hv = torch.from_numpy(np.ascontiguousarray(case.vals.reshape(-1)))
+            S_mix.update_values(hv if k % 2 else hv.numpy())
+        out = [S.solve(_dev(b), tol=1e-6) for S in (S_dev, S_host, S_mix)]
+        x0 = out[0][0].cpu().numpy()
+        for x, info in out[1:]:
+            assert info["iterations"] == out[0][1]["iterations"], k
+            assert info["rebuilt"] == out[0][1]["rebuilt"], k
+            assert np.array_equal(x.cpu().numpy(), x0), k
+    for S in (S_dev, S_host, S_mix):
+        S.close()
+
+
 def test_error_paths(sequence):
     from paper_2201_01970_amd import CprError, Params, Solver
     from paper_2201_01970_amd import _capi as capi
