@@ -5,7 +5,8 @@ grid with 2.5% inactive cells (23400 cells: many 64-row slices and a ragged
 last slice).  Bars:
   * bit for bit: the BSR product, GPU strength masks, colours, C/F split,
     interpolation weights, Galerkin matrices and the PGS-SCM sweeps (every sum
-    runs in the oracle's order without FMA contraction);
+    runs in the oracle's order without FMA contraction), and the FP32
+    preconditioner's sweeps against the oracle's sweep on float32 arrays;
   * 1e-12 relative: the V-cycle and CPR apply (the coarsest LU is factored by
     a different routine than the oracle's LAPACK call);
   * FP64 solve: same iteration count, iterate within 1e-10 relative;
@@ -108,6 +109,30 @@ def test_smoother_bit_exact(setup_pair):
             amg.colour_sweep(lev.A, lev.colours, want, bb)
         got = S.smooth(l, _dev(np.zeros_like(bb)), _dev(bb), sweeps=2, zero_start=True).cpu().numpy()
         assert np.array_equal(got, want), l
+
+
+def test_fp32_smoother_bit_exact_with_fp32_oracle(setup_pair):
+    """The FP32 preconditioner's sweeps round every product, difference and
+    quotient to single precision in the oracle's order, so they equal the
+    oracle's sweep run on float32 arrays (matrix, x, b and diagonal rounded
+    to float32) bit for bit, on every level and from both starts."""
+    name, case, A, B, b, S0 = setup_pair
+    H = B.amg
+    S = _solver(case, precond_fp32=True)
+    rng = np.random.default_rng(12)
+    for l in range(H.n_levels - 1):
+        lev = H.levels[l]
+        A32 = Csr(lev.A.n_rows, lev.A.n_cols, lev.A.indptr, lev.A.indices, lev.A.data.astype(np.float32))
+        d32 = lev.diag.astype(np.float32)
+        bb = rng.standard_normal(lev.A.n_rows)
+        for zero_start in (False, True):
+            x0 = np.zeros_like(bb) if zero_start else rng.standard_normal(lev.A.n_rows)
+            want = x0.astype(np.float32)
+            for _ in range(2):
+                amg.colour_sweep(A32, lev.colours, want, bb.astype(np.float32), d32)
+            got = S.smooth(l, _dev(x0.copy()), _dev(bb), sweeps=2, zero_start=zero_start).cpu().numpy()
+            assert np.array_equal(got, want.astype(np.float64)), (l, zero_start)
+    S.close()
 
 
 @pytest.mark.parametrize("tail_nnz", [0, 30000, 10 ** 9])
