@@ -213,28 +213,37 @@ def test_tail_with_large_coarsest_level(setup_pair, fp32):
     S_ref.close()
 
 
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
 @pytest.mark.parametrize("layout", [1, 2, 4, 16, 32, 64])
-def test_every_row_layout_bit_identical(setup_pair, layout):
+def test_every_row_layout_bit_identical(setup_pair, layout, fp32):
     """Every storage form of the level matrices (1: SELL-64, one lane per row;
     2: 16 lanes with four contiguous entries each; 4: quad-vector; 16/32/64:
-    one entry per lane) gives the oracle's PGS-SCM sweeps bit for bit and the
-    same V-cycle bit for bit as the default forms, since every row sum runs in
+    one entry per lane), in both precisions, gives the oracle's PGS-SCM sweeps
+    bit for bit (FP32: the oracle's sweep on float32 arrays) and the same
+    V-cycle bit for bit as the default forms, since every row sum runs in
     stored order."""
     name, case, A, B, b, S0 = setup_pair
-    S = _solver(case, row_layout=layout, tail_nnz=0)
+    S = _solver(case, row_layout=layout, tail_nnz=0, precond_fp32=fp32)
     H = B.amg
+    dt = np.float32 if fp32 else np.float64
     rng = np.random.default_rng(11)
     for l in range(H.n_levels - 1):
         lev = H.levels[l]
+        Al = Csr(lev.A.n_rows, lev.A.n_cols, lev.A.indptr, lev.A.indices, lev.A.data.astype(dt))
         bb = rng.standard_normal(lev.A.n_rows)
         x0 = rng.standard_normal(lev.A.n_rows)
-        want = x0.copy()
-        for _ in range(2):
-            amg.colour_sweep(lev.A, lev.colours, want, bb)
-        got = S.smooth(l, _dev(x0.copy()), _dev(bb), sweeps=2, zero_start=False).cpu().numpy()
-        assert np.array_equal(got, want), (layout, l)
+        for zero_start in (False, True):
+            want = np.zeros(lev.A.n_rows, dt) if zero_start else x0.astype(dt)
+            for _ in range(2):
+                amg.colour_sweep(Al, lev.colours, want, bb.astype(dt), lev.diag.astype(dt))
+            xin = np.zeros_like(x0) if zero_start else x0.copy()
+            got = S.smooth(l, _dev(xin), _dev(bb), sweeps=2, zero_start=zero_start).cpu().numpy()
+            assert np.array_equal(got, want.astype(np.float64)), (layout, l, zero_start)
     r = rng.standard_normal(A.n_b)
-    assert np.array_equal(S.vcycle(_dev(r)).cpu().numpy(), S0.vcycle(_dev(r)).cpu().numpy())
+    S_def = _solver(case, tail_nnz=0, precond_fp32=fp32) if fp32 else S0
+    assert np.array_equal(S.vcycle(_dev(r)).cpu().numpy(), S_def.vcycle(_dev(r)).cpu().numpy())
+    if fp32:
+        S_def.close()
     S.close()
 
 
