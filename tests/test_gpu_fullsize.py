@@ -5,7 +5,8 @@ configuration the benchmark times, checked where the oracle can follow:
   the oracle's ordered sum (bit for bit);
 * the GPU strength masks of level 0 on sampled rows against the oracle's
   definitions (bit for bit);
-* one PGS-SCM sweep on each of levels 0-3 on sampled rows: each sampled row
+* one PGS-SCM sweep on each of levels 0-3 on sampled rows, FP64 and FP32
+  (against the oracle on float32 arrays): each sampled row
   is recomputed by the oracle's colour sweep from the values the sweep saw
   when its colour started (the GPU's output on earlier colours, the start
   values elsewhere), bit for bit;
@@ -109,31 +110,34 @@ def test_fullsize_sweeps_sampled_rows(big):
     from paper_2201_01970_amd import Params, Solver
 
     case, b = big
-    S = Solver(_dev(case.row_ptr), _dev(case.col), _dev(case.vals.reshape(-1)), Params())
-    rng = np.random.default_rng(31)
-    for l in range(4):
-        lv = S.level_arrays(l)
-        n = lv["row_ptr"].size - 1
-        A = Csr(n, n, lv["row_ptr"].astype(np.int64), lv["col"].astype(np.int64), lv["val"])
-        colour = lv["colour"]
-        rows = _sample_rows(n, 4000, 40 + l)
-        diag = np.zeros(n)
-        for i in rows:
-            c, v = A.row(i)
-            diag[i] = v[c == i][0]
-        bb = rng.standard_normal(n)
-        for zero_start in ((False, True) if l == 0 else (False,)):
-            x0 = np.zeros(n) if zero_start else rng.standard_normal(n)
-            got = S.smooth(l, _dev(x0.copy()), _dev(bb), sweeps=1, zero_start=zero_start).cpu().numpy()
-            for k in range(int(colour.max()) + 1):
-                rk = rows[colour[rows] == k]
-                if rk.size == 0:
-                    continue
-                snap = np.where(colour < k, got, x0)
-                amg.colour_sweep(A, [rk], snap, bb, diag)
-                assert np.array_equal(snap[rk], got[rk]), (l, k, zero_start)
-            print(f"[fullsize] level {l} n={n} sweep on {rows.size} sampled rows bit-exact", flush=True)
-    S.close()
+    for fp32 in (False, True):
+        dt = np.float32 if fp32 else np.float64
+        S = Solver(_dev(case.row_ptr), _dev(case.col), _dev(case.vals.reshape(-1)), Params(precond_fp32=fp32))
+        rng = np.random.default_rng(31)
+        for l in range(4):
+            lv = S.level_arrays(l)
+            n = lv["row_ptr"].size - 1
+            A = Csr(n, n, lv["row_ptr"].astype(np.int64), lv["col"].astype(np.int64), lv["val"].astype(dt))
+            colour = lv["colour"]
+            rows = _sample_rows(n, 4000, 40 + l)
+            diag = np.zeros(n, dt)
+            for i in rows:
+                c, v = A.row(i)
+                diag[i] = v[c == i][0]
+            bb = rng.standard_normal(n)
+            for zero_start in ((False, True) if l == 0 else (False,)):
+                x0 = np.zeros(n) if zero_start else rng.standard_normal(n)
+                got = S.smooth(l, _dev(x0.copy()), _dev(bb), sweeps=1, zero_start=zero_start).cpu().numpy()
+                for k in range(int(colour.max()) + 1):
+                    rk = rows[colour[rows] == k]
+                    if rk.size == 0:
+                        continue
+                    # got holds float32 values exactly when the sweep ran in FP32
+                    snap = np.where(colour < k, got, x0).astype(dt)
+                    amg.colour_sweep(A, [rk], snap, bb.astype(dt), diag)
+                    assert np.array_equal(snap[rk].astype(np.float64), got[rk]), (fp32, l, k, zero_start)
+            print(f"[fullsize] fp32={fp32} level {l} n={n} sweep on {rows.size} sampled rows bit-exact", flush=True)
+        S.close()
 
 
 def _rs_mask_rowwise(A, theta):
