@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 from oracle import amg, cpr, fgmres
+from oracle.sparse import Csr
 from workloads import blackoil as bo
 
 pytestmark = pytest.mark.gpu
@@ -79,7 +80,9 @@ def test_channelised_small_grids_match_oracle(shape):
     """Channelised permeability (1000 mD channels on 1 mD, kz/kx 0.01): 2-3
     colours on level 0 and 5 on the coarse levels, 6-7 levels.  FP64 solve
     with the oracle's iteration count and iterate within 1e-10 relative; the
-    smoothers bit for bit on every level."""
+    smoothers bit for bit on every level, in FP64 and in FP32 (against the
+    oracle on float32 arrays); the FP32-preconditioned solve converged with
+    iterations within 10%."""
     case = bo.case_channels(seed=21, shape=shape)
     print(f"[channels {shape}] n_b={case.n_b}", flush=True)
     A = cpr.Bsr.from_case(case)
@@ -102,3 +105,20 @@ def test_channelised_small_grids_match_oracle(shape):
         got = S.smooth(l, _dev(x0.copy()), _dev(bb), sweeps=2, zero_start=False).cpu().numpy()
         assert np.array_equal(got, want), l
     S.close()
+
+    # the FP32 preconditioner: sweeps against the oracle's sweep on float32 arrays
+    S32 = _solver(case, precond_fp32=True)
+    for l in range(B.amg.n_levels - 1):
+        lev = B.amg.levels[l]
+        A32 = Csr(lev.A.n_rows, lev.A.n_cols, lev.A.indptr, lev.A.indices, lev.A.data.astype(np.float32))
+        bb = rng.standard_normal(lev.A.n_rows)
+        x0 = rng.standard_normal(lev.A.n_rows)
+        want = x0.astype(np.float32)
+        for _ in range(2):
+            amg.colour_sweep(A32, lev.colours, want, bb.astype(np.float32), lev.diag.astype(np.float32))
+        got = S32.smooth(l, _dev(x0.copy()), _dev(bb), sweeps=2, zero_start=False).cpu().numpy()
+        assert np.array_equal(got, want.astype(np.float64)), ("fp32", l)
+    x32, info32 = S32.solve(_dev(b), tol=1e-6)
+    assert info32["relres_true"] < 1e-6
+    assert abs(info32["iterations"] - info["iterations"]) <= max(1, 0.1 * info["iterations"])
+    S32.close()
