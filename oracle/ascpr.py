@@ -45,6 +45,7 @@ class StepReport:
     iterations: int
     relres_true: float
     converged: bool
+    x: np.ndarray | None = None  # the step's iterate
 
 
 def solve_sequence(steps, params: AmgParams | None = None, tol=1e-6, m=30, mode="factor",
@@ -63,5 +64,5 @@ def solve_sequence(steps, params: AmgParams | None = None, tol=1e-6, m=30, mode=
         if rebuild:
             it_ref = res.iterations
         n_prev = A.n_b
-        reports.append(StepReport(k, rebuild, res.iterations, res.relres_true, res.converged))
+        reports.append(StepReport(k, rebuild, res.iterations, res.relres_true, res.converged, res.x))
     return reports

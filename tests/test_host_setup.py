@@ -124,3 +124,23 @@ def test_rs_split_random_graphs_bit_exact():
         ix = np.array([j for s in S for j in s], dtype=np.int64)
         got = host_rs_split(ip, ix)
         assert np.array_equal(got, want)
+
+
+def test_interpolation_hand_derived_strong_f_neighbours():
+    """The library's RS interpolation on the hand-worked case of test_oracle_rs:
+    equal to the oracle bit for bit and to the exact rational weights."""
+    from paper_2201_01970_amd import host_interpolation
+    from test_oracle_rs import hand_case, hand_expected_dense
+
+    A, mask, state = hand_case()
+    p_ptr, p_col, p_val, nc = host_interpolation(*_csr32(A), mask.astype(np.uint8), state)
+    P = rs.interpolation(A, mask, state)
+    assert nc == 3
+    assert np.array_equal(p_ptr, P.indptr)
+    assert np.array_equal(p_col, P.indices)
+    assert np.array_equal(p_val, P.data)
+    got = np.zeros((6, 3))
+    for i in range(6):
+        for k in range(p_ptr[i], p_ptr[i + 1]):
+            got[i, p_col[k]] = p_val[k]
+    assert np.allclose(got, hand_expected_dense(), rtol=4e-16, atol=0.0)

@@ -131,3 +131,98 @@ def test_split_invariants_on_random_m_matrices():
         # interpolation reproduces constants where rows of A sum to ~0 only
         # approximately; check the weights are positive for M-matrices
         assert (P.data > 0).all()
+
+
+# ---------------------------------------------------------------------------
+# Hand-derived classical interpolation with strong F-F couplings.
+#
+# Six points; the C/F state and the strength pattern are given by hand (the
+# interpolation formula is pinned on its own, independent of the split):
+#   F = {0, 1, 5}, C = {2, 3, 4} (coarse indices 0, 1, 2).
+# Row 0: a00 = 10, a01 = -2 (strong, F), a02 = -3 (strong, C), a03 = -1
+#        (strong, C), a04 = -0.5 (weak), a05 = -1.5 (strong, F).
+# Row 1: a10 = -1 (strong, F), a11 = 8, a12 = -4, a13 = -2 (strong, C).
+# Row 5: a50 = -1 (strong, F), a54 = -2 (strong, C), a55 = 4.
+# Rows 2-4 (C points) carry entries that a transposed index would pick up.
+#
+# Textbook RS interpolation (Briggs, Henson, McCormick, ch. 8):
+#   w_ij = -(a_ij + sum_{m strong F} a_im a_mj / sum_{k in C_i} a_mk)
+#          / (a_ii + sum_{n weak} a_in)
+# with a strong F neighbour that meets no point of C_i lumped into the
+# diagonal.  Worked by hand:
+#   row 0: C_0 = {2, 3}.  m = 1: denominator a12 + a13 = -6, so
+#          num_2 = -3 + (-2)(-4)/(-6) = -13/3, num_3 = -1 + (-2)(-2)/(-6) = -5/3.
+#          m = 5 meets neither 2 nor 3 (denominator 0): lumped.
+#          d = 10 - 0.5 - 1.5 = 8, so w_02 = 13/24, w_03 = 5/24.
+#   row 1: C_1 = {2, 3}.  m = 0: denominator a02 + a03 = -4, so
+#          num_2 = -4 + (-1)(-3)/(-4) = -19/4, num_3 = -2 + (-1)(-1)/(-4) = -9/4;
+#          d = 8, so w_12 = 19/32, w_13 = 9/32.
+#   row 5: C_5 = {4}.  m = 0: denominator a04 = -1/2, so
+#          num_4 = -2 + (-1)(-1/2)/(-1/2) = -3; d = 4, so w_54 = 3/4.
+# Lumping every strong F neighbour instead (row 0: d = 6) gives w_02 = 1/2;
+# reading a_km for a_mk, or summing the denominator over all of row m, also
+# changes these weights.
+# ---------------------------------------------------------------------------
+from fractions import Fraction as Q  # noqa: E402
+
+from oracle.sparse import Csr  # noqa: E402
+
+_HAND_ROWS = {
+    0: [(0, 10.0), (1, -2.0), (2, -3.0), (3, -1.0), (4, -0.5), (5, -1.5)],
+    1: [(0, -1.0), (1, 8.0), (2, -4.0), (3, -2.0)],
+    2: [(0, -1.1), (1, -0.7), (2, 5.0), (4, -1.0)],
+    3: [(0, -0.9), (1, -1.3), (3, 6.0)],
+    4: [(0, -0.2), (2, -1.5), (4, 3.0), (5, -0.25)],
+    5: [(0, -1.0), (4, -2.0), (5, 4.0)],
+}
+# strong dependencies of the F rows (C rows are never interpolated)
+_HAND_STRONG = {0: {1, 2, 3, 5}, 1: {0, 2, 3}, 5: {0, 4}}
+_HAND_STATE = [rs.F, rs.F, rs.C, rs.C, rs.C, rs.F]
+_HAND_P = {  # row -> {coarse column: exact weight}
+    0: {0: Q(13, 24), 1: Q(5, 24)},
+    1: {0: Q(19, 32), 1: Q(9, 32)},
+    2: {0: Q(1)},
+    3: {1: Q(1)},
+    4: {2: Q(1)},
+    5: {2: Q(3, 4)},
+}
+
+
+def hand_case():
+    """The hand-built matrix, its strength mask and C/F state (also used by the C++ check)."""
+    indptr, indices, data, mask = [0], [], [], []
+    for i in range(6):
+        for j, v in _HAND_ROWS[i]:
+            indices.append(j)
+            data.append(v)
+            mask.append(j in _HAND_STRONG.get(i, set()))
+        indptr.append(len(indices))
+    A = Csr(6, 6, np.array(indptr, dtype=np.int64), np.array(indices, dtype=np.int64),
+            np.array(data, dtype=np.float64))
+    return A, np.array(mask, dtype=bool), np.array(_HAND_STATE, dtype=np.int8)
+
+
+def hand_expected_dense():
+    P = np.zeros((6, 3))
+    for i, row in _HAND_P.items():
+        for J, w in row.items():
+            P[i, J] = float(w)
+    return P
+
+
+def test_interpolation_strong_f_neighbours_hand_derived():
+    A, mask, state = hand_case()
+    # the hand-given strength pattern is what classical RS strength gives at 0.25
+    rs_mask, _ = strength.rs_strength(A, 0.25)
+    for i in (0, 1, 5):
+        a, b = A.indptr[i], A.indptr[i + 1]
+        assert list(rs_mask[a:b]) == list(mask[a:b])
+    P = rs.interpolation(A, mask, state)
+    assert P.n_cols == 3
+    want = hand_expected_dense()
+    got = P.to_dense()
+    assert np.allclose(got, want, rtol=4e-16, atol=0.0), (got, want)
+    # every weight within one rounding of the exact rational
+    for i, row in _HAND_P.items():
+        for J, w in row.items():
+            assert abs(Q(got[i, J]) - w) <= abs(w) * Q(1, 2 ** 51)

@@ -89,3 +89,28 @@ def test_factor_rule_follows_history():
         if r.rebuilt:
             it_ref = r.iterations
         prev = r.iterations
+
+
+def test_reuse_freezes_the_whole_preconditioner():
+    """Algorithm "ASCPR" keeps B^(k) = B^(k-1): a reused step runs FGMRES on the
+    new A^(k) with the operator built from the matrix of the last SETUP,
+    including the copy of A inside the CPR apply (stage-2 residual and block
+    GS).  Pinned against an explicit construction: step 2 equals FGMRES on A1
+    preconditioned by setup(A0), and differs from a preconditioner that
+    rebuilds only the fine-level residual with A1."""
+    steps = _sequence(n=2)
+    reps = ascpr.solve_sequence(steps, mode="mu", mu=10 ** 9)
+    assert [r.rebuilt for r in reps] == [True, False]
+    (A0, _), (A1, b1) = steps
+    B0 = cpr.setup(A0)
+    want = fgmres.fgmres(lambda v: cpr.bsr_matvec(A1, v), B0.apply, b1)
+    assert reps[1].iterations == want.iterations
+    assert np.array_equal(reps[1].x, want.x)
+    # the frozen operator ignores later changes of the caller's matrix
+    v = bo.rhs(3 * A0.n_b, 77)
+    z0 = B0.apply(v)
+    A0.vals[:] = A1.vals
+    assert np.array_equal(B0.apply(v), z0)
+    # the alternative reading (current A inside the apply) is a different operator
+    B_mixed = cpr.CprPreconditioner(A=A1, amg=B0.amg, block_colours=B0.block_colours, Dinv=B0.Dinv)
+    assert not np.array_equal(B_mixed.apply(v), z0)
