@@ -75,7 +75,9 @@ typedef struct {
                              outer FGMRES, FP64 coarsest solve) [0] */
   int32_t reuse_mode;     /* 0: SETUP before every solve on new values;
                              1: paper rule, reuse iff It^(k-1) <= mu;
-                             2: relative rule, reuse iff It^(k-1) <= reuse_factor*It_ref [2] */
+                             2: relative rule, reuse iff It^(k-1) <= reuse_factor*It_ref [2].
+                             In every mode, values changed before the first solve
+                             trigger a SETUP for it (k = 1) */
   int32_t mu;             /* threshold of reuse_mode 1 [20] */
   double reuse_factor;    /* factor of reuse_mode 2 [1.3] */
   int32_t use_graphs;     /* 1: replay each FGMRES step as one captured HIP graph [1] */
@@ -119,11 +121,16 @@ void cpr_params_default(cpr_params* p);
 cpr_status cpr_setup(const cpr_bsr* A, const cpr_params* p, void* hip_stream, cpr_handle** out);
 
 /* Replace the values of A (same n_block_rows, nnz_blocks, row_ptr, col_idx;
- * the pattern is compared through a 64-bit hash).  The outer FGMRES uses the
- * new values at the next solve; whether the preconditioner is rebuilt is
- * decided there by the adaptive rule (Algorithm "ASCPR"); a singular diagonal
- * block is reported by the solve that rebuilds.  Errors:
- * CPR_ERR_SIZE_MISMATCH, CPR_ERR_PATTERN_MISMATCH. */
+ * the pattern is compared entry by entry with the one given to cpr_setup, on
+ * the device for device arrays).  The outer FGMRES uses the new values at the
+ * next solve; whether the preconditioner is rebuilt is decided there by the
+ * adaptive rule (Algorithm "ASCPR"): new values before the handle's first
+ * solve always rebuild (solve k = 1 runs on a B of the matrix it solves),
+ * reuse_mode 0 rebuilds on every new set of values, modes 1 and 2 keep B
+ * frozen (every SETUP product, including the copy of A inside the CPR apply)
+ * while their rule allows.  A singular diagonal block is reported by the solve
+ * that rebuilds; a failed rebuild leaves the previous B in the handle.
+ * Errors: CPR_ERR_SIZE_MISMATCH, CPR_ERR_PATTERN_MISMATCH. */
 cpr_status cpr_update_values(cpr_handle* h, const cpr_bsr* A);
 
 /* Solve A x = b to ||b - A x|| / ||b - A x_in|| < tol with CPR-FGMRES

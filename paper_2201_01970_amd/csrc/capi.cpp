@@ -68,6 +68,13 @@ void check_bsr(const cpr_bsr* A) {
     throw Error(CPR_ERR_INVALID_ARG, "location must be CPR_MEM_HOST or CPR_MEM_DEVICE");
 }
 
+// SETUP builds a new preconditioner aside and swaps it in only on success, so
+// a handle that cpr_setup returned always holds one; checked anyway before any
+// entry point dereferences it.
+void need_pc(const cpr_handle* h) {
+  if (!h->pc) throw Error(CPR_ERR_INVALID_ARG, "the handle holds no preconditioner");
+}
+
 // Outer FP64 block SELL in natural row order; pos[k] = lane-slot of block k.
 void build_outer(cpr_handle* h) {
   const int32_t n = h->n_b;
@@ -259,7 +266,10 @@ cpr_status cpr_update_values(cpr_handle* h, const cpr_bsr* A) {
 cpr_status cpr_solve(cpr_handle* h, const double* b, double* x, double tol, cpr_solve_info* info) {
   if (!h) return fail(nullptr, CPR_ERR_INVALID_ARG, "null handle");
   if (!b || !x || !(tol > 0.0)) return fail(h, CPR_ERR_INVALID_ARG, "b, x must be device arrays and tol > 0");
-  return guarded(h, [&]() -> cpr_status { return h->solve(b, x, tol, info); });
+  return guarded(h, [&]() -> cpr_status {
+    need_pc(h);
+    return h->solve(b, x, tol, info);
+  });
 }
 
 cpr_status cpr_set_stream(cpr_handle* h, void* hip_stream) {
@@ -321,6 +331,7 @@ cpr_status cpr_spmv(cpr_handle* h, const double* x, double* y) {
 cpr_status cpr_precond_apply(cpr_handle* h, const double* v, double* z) {
   if (!h || !v || !z) return fail(h, CPR_ERR_INVALID_ARG, "null argument");
   return guarded(h, [&]() -> cpr_status {
+    need_pc(h);
     if (h->pc->fp32()) {
       h->pc->apply(v, h->Z, h->stream);
       launch_copy_cast<float, double>(3 * static_cast<int64_t>(h->n_b), static_cast<const float*>(h->Z), z,
@@ -336,6 +347,7 @@ cpr_status cpr_precond_apply(cpr_handle* h, const double* v, double* z) {
 cpr_status cpr_vcycle(cpr_handle* h, const double* r, double* e) {
   if (!h || !r || !e) return fail(h, CPR_ERR_INVALID_ARG, "null argument");
   return guarded(h, [&]() -> cpr_status {
+    need_pc(h);
     h->pc->vcycle_own(r, e, h->stream);
     HIPCHK(hipStreamSynchronize(h->stream));
     return CPR_OK;
@@ -346,6 +358,7 @@ cpr_status cpr_smooth(cpr_handle* h, int32_t level, double* x, const double* b, 
                       int32_t zero_start) {
   if (!h || !x || !b || n_sweeps < 0) return fail(h, CPR_ERR_INVALID_ARG, "invalid argument");
   return guarded(h, [&]() -> cpr_status {
+    need_pc(h);
     h->pc->smooth_own(level, x, b, n_sweeps, zero_start != 0, h->stream);
     HIPCHK(hipStreamSynchronize(h->stream));
     return CPR_OK;

@@ -140,8 +140,9 @@ using namespace cpr;
 void cpr_handle::build_precond() {
   const double t0 = now_ms();
   drop_graphs();
-  pc.reset();
-  hl.clear();
+  // Everything is built into locals and swapped into the handle only when the
+  // whole SETUP succeeded: a failed rebuild leaves the previous B in place.
+  std::vector<HostLevel> hl;
 
   // SETUP's view of the values, prepared on the device from the handle's
   // copy of A: the pressure entry of every block, which blocks hold a nonzero
@@ -290,14 +291,16 @@ void cpr_handle::build_precond() {
   Colouring bc = block_task.get();
   const double t_colour_wait = now_ms() - tp;
   tp = now_ms();
-  block_colour = std::move(bc.colour);
-  n_block_colours = bc.n_colours;
   std::vector<int32_t> bperm = std::move(bc.perm), bcoff = std::move(bc.coff);
 
-  pc = make_precond(prm.precond_fp32 != 0, prm, n_b, hl, lu, piv, bperm, bcoff, h_row_ptr, h_col, block_colour,
-                    d_vals_in, stream);
-  pc->timer = &prof;
+  std::unique_ptr<PrecondBase> npc = make_precond(prm.precond_fp32 != 0, prm, n_b, hl, lu, piv, bperm, bcoff,
+                                                  h_row_ptr, h_col, bc.colour, d_vals_in, stream);
+  npc->timer = &prof;
   HIPCHK(hipStreamSynchronize(stream));
+  pc = std::move(npc);
+  this->hl.swap(hl);
+  block_colour = std::move(bc.colour);
+  n_block_colours = bc.n_colours;
   values_changed = false;
   last_setup_ms = now_ms() - t0;
   if (std::getenv("CPR_SETUP_TRACE"))
@@ -379,10 +382,13 @@ void cpr_handle::step_body(int j, hipStream_t s) {
 // confirmed with the true residual; iterations = inner steps.
 cpr_status cpr_handle::solve(const double* b, double* x, double tol, cpr_solve_info* info) {
   // adaptive setup (Algorithm "ASCPR"); SETUP of cpr_setup counts as k = 1
+  // k counts solves since the handle's SETUP.  Solve k = 1 always runs on a B
+  // built from the matrix it solves: cpr_setup built it, unless new values
+  // arrived before this first solve, in which case SETUP runs again.
   k_solves += 1;
   bool rebuild = false;
-  if (k_solves > 1 && values_changed) {
-    if (prm.reuse_mode == 0)
+  if (values_changed) {
+    if (k_solves == 1 || prm.reuse_mode == 0)
       rebuild = true;
     else if (prm.reuse_mode == 1)
       rebuild = !(it_prev <= prm.mu);

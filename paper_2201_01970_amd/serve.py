@@ -25,7 +25,15 @@ class Server:
         rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
         cl = np.ascontiguousarray(col, dtype=np.int32)
         vv = np.ascontiguousarray(vals, dtype=np.float64).reshape(-1)
-        bb = np.ascontiguousarray(b, dtype=np.float64)
+        bb = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
+        n, nnz = rp.shape[0] - 1, cl.shape[0]
+        # the library reads vals as double[9 * nnz] and b, x as double[3 * n]
+        if n < 1 or nnz < 1:
+            raise ValueError("row_ptr must hold at least two entries and col at least one")
+        if vv.shape[0] != 9 * nnz:
+            raise ValueError(f"vals must hold 9 * nnz_blocks = {9 * nnz} entries, got {vv.shape[0]}")
+        if bb.shape[0] != 3 * n:
+            raise ValueError(f"b must hold 3 * n_block_rows = {3 * n} entries, got {bb.shape[0]}")
         x = np.zeros_like(bb)
         req = A.cpr_request(int(case_id), A.cpr_bsr(rp.shape[0] - 1, cl.shape[0], 3, rp.ctypes.data,
                                                    cl.ctypes.data, vv.ctypes.data, A.CPR_MEM_HOST),

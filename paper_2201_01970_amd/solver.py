@@ -52,6 +52,31 @@ def _host(arr):
     return arr if isinstance(arr, np.ndarray) else arr.detach().cpu().numpy()
 
 
+def _check_device_vec(t, n, name, device):
+    """Raise ValueError unless t is a contiguous float64 tensor of n entries on
+    the handle's HIP device: the library reads and writes it as double[n]."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor on the GPU, got {type(t).__name__}")
+    if not t.is_cuda or (device is not None and t.device != device):
+        raise ValueError(f"{name} must live on {device}, got {t.device}")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} must hold {n} entries, got {t.numel()}")
+
+
+def _check_bsr_sizes(n, nnz, n_vals):
+    if n < 1:
+        raise ValueError("row_ptr must hold at least two entries")
+    if nnz < 1:
+        raise ValueError("col must not be empty")
+    if n_vals != 9 * nnz:
+        raise ValueError(f"vals must hold 9 * nnz_blocks = {9 * nnz} entries, got {n_vals}")
+
+
 def _ptr(arr):
     """Address of a contiguous numpy array or torch tensor."""
     if isinstance(arr, np.ndarray):
@@ -68,6 +93,7 @@ class Solver:
         torch = _torch()
         self._lib = A.lib()
         self.params = params or Params()
+        self.device = torch.device("cuda", torch.cuda.current_device())
         self._keep = self._as_bsr(row_ptr, col, vals)
         self.n_b = int(self._bsr.n_block_rows)
         self.nnz_b = int(self._bsr.nnz_blocks)
@@ -95,6 +121,7 @@ class Solver:
             rp, cl = rp.to(vv.device), cl.to(vv.device)
         n = int(rp.shape[0]) - 1
         nnz = int(cl.shape[0])
+        _check_bsr_sizes(n, nnz, int(vv.shape[0]))
         self._bsr = A.cpr_bsr(n, nnz, 3, _ptr(rp), _ptr(cl), _ptr(vv), loc)
         return (rp, cl, vv)
 
@@ -109,9 +136,10 @@ class Solver:
 
     def solve(self, b, x=None, tol=1e-6, allow_not_converged=False):
         torch = _torch()
-        b = b.contiguous()
+        _check_device_vec(b, 3 * self.n_b, "b", self.device)
         if x is None:
             x = torch.zeros_like(b)
+        _check_device_vec(x, 3 * self.n_b, "x", self.device)
         info = A.cpr_solve_info()
         st = self._lib.cpr_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), float(tol),
                                  C.byref(info))
@@ -123,23 +151,32 @@ class Solver:
 
     def spmv(self, x, y=None):
         torch = _torch()
+        _check_device_vec(x, 3 * self.n_b, "x", self.device)
         y = torch.empty_like(x) if y is None else y
+        _check_device_vec(y, 3 * self.n_b, "y", self.device)
         A.check(self._lib.cpr_spmv(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())), self._h)
         return y
 
     def precond(self, v, z=None):
         torch = _torch()
+        _check_device_vec(v, 3 * self.n_b, "v", self.device)
         z = torch.empty_like(v) if z is None else z
+        _check_device_vec(z, 3 * self.n_b, "z", self.device)
         A.check(self._lib.cpr_precond_apply(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(z.data_ptr())), self._h)
         return z
 
     def vcycle(self, r, e=None):
         torch = _torch()
+        _check_device_vec(r, self.n_b, "r", self.device)
         e = torch.empty_like(r) if e is None else e
+        _check_device_vec(e, self.n_b, "e", self.device)
         A.check(self._lib.cpr_vcycle(self._h, C.c_void_p(r.data_ptr()), C.c_void_p(e.data_ptr())), self._h)
         return e
 
     def smooth(self, level, x, b, sweeps=1, zero_start=False):
+        n = self.level_info(level)["n"]
+        _check_device_vec(x, n, "x", self.device)
+        _check_device_vec(b, n, "b", self.device)
         A.check(self._lib.cpr_smooth(self._h, int(level), C.c_void_p(x.data_ptr()), C.c_void_p(b.data_ptr()),
                                      int(sweeps), int(bool(zero_start))), self._h)
         return x

@@ -5,7 +5,12 @@ The sequence is the drifting-Jacobian generator (fixed pattern, +-5% value
 drift per step) on a 16x14x8 grid.  For each rule the GPU's rebuild
 decisions and iteration counts must equal the oracle's step by step (the
 decisions are a pure function of the iteration history, so they must agree
-exactly), and every step must reach the true relative residual.
+exactly), every step must reach the true relative residual, and in FP64 every
+step's iterate must match the oracle's within 1e-10 relative (reused steps
+included: they run on the frozen B of the last SETUP).  Also: new values
+before the first solve rebuild in every mode; reuse_mode 0 rebuilds on every
+new set of values; a reused B is bit-identical before and after new values
+arrive; a failed rebuild leaves the previous B usable.
 """
 import numpy as np
 import pytest
@@ -59,6 +64,8 @@ def test_sequence_matches_oracle(sequence, rule, fp32):
             assert bool(info["rebuilt"]) == rep.rebuilt
         if not fp32:
             assert info["iterations"] == rep.iterations
+            xg = x.cpu().numpy()
+            assert np.linalg.norm(xg - rep.x) <= 1e-10 * np.linalg.norm(rep.x), k
         else:
             assert abs(info["iterations"] - rep.iterations) <= max(1, 0.1 * rep.iterations)
     S.close()
@@ -147,3 +154,75 @@ def test_invalid_matrices_rejected():
     with pytest.raises(CprError) as e:
         Solver(rp, col, vals2, Params())
     assert e.value.status == capi.CPR_ERR_SINGULAR_BLOCK
+
+
+@pytest.mark.parametrize("reuse_mode", [0, 1, 2])
+def test_values_before_first_solve_rebuild(sequence, reuse_mode):
+    """setup(A0), update_values(A1), solve: the first solve runs on a B built
+    from A1 (the oracle's solve k = 1 sets up on the matrix it solves)."""
+    from paper_2201_01970_amd import Params, Solver
+
+    steps = [(cpr.Bsr.from_case(c), b) for c, b in sequence[1:4]]
+    mode = {0: "never", 1: "mu", 2: "factor"}[reuse_mode]
+    reps = ascpr.solve_sequence(steps, mode=mode, mu=6, factor=1.3)
+    c0 = sequence[0][0]
+    S = Solver(_dev(c0.row_ptr), _dev(c0.col), _dev(c0.vals.reshape(-1)),
+               Params(reuse_mode=reuse_mode, mu=6, reuse_factor=1.3))
+    for k, ((A, b), rep) in enumerate(zip(steps, reps)):
+        S.update_values(_dev(A.vals.reshape(-1)))
+        x, info = S.solve(_dev(b), tol=1e-6)
+        print(f"[first-solve mode {reuse_mode}] step {k}: gpu its={info['iterations']} rebuilt={info['rebuilt']} "
+              f"| oracle its={rep.iterations} rebuilt={rep.rebuilt}", flush=True)
+        assert bool(info["rebuilt"]) == rep.rebuilt, k
+        assert info["iterations"] == rep.iterations, k
+        assert np.linalg.norm(x.cpu().numpy() - rep.x) <= 1e-10 * np.linalg.norm(rep.x), k
+    if reuse_mode == 0:
+        assert all(r.rebuilt for r in reps)
+    S.close()
+
+
+def test_reused_operator_is_frozen(sequence):
+    """New values do not touch a reused B: cpr_precond_apply gives the same
+    bits before update_values, after it, and after a solve that reused B."""
+    from paper_2201_01970_amd import Params, Solver
+
+    (c0, b0), (c1, b1) = sequence[0], sequence[1]
+    S = Solver(_dev(c0.row_ptr), _dev(c0.col), _dev(c0.vals.reshape(-1)), Params(reuse_mode=1, mu=10 ** 6))
+    S.solve(_dev(b0), tol=1e-6)
+    v = _dev(bo.rhs(c0.ndof, 91))
+    z_before = S.precond(v).cpu().numpy()
+    S.update_values(_dev(c1.vals.reshape(-1)))
+    assert np.array_equal(S.precond(v).cpu().numpy(), z_before)
+    x, info = S.solve(_dev(b1), tol=1e-6)
+    assert info["rebuilt"] == 0
+    assert np.array_equal(S.precond(v).cpu().numpy(), z_before)
+    # the oracle's frozen operator (SETUP on A0) gives the same z within 1e-12
+    B0 = cpr.setup(cpr.Bsr.from_case(c0))
+    z_or = B0.apply(v.cpu().numpy())
+    assert np.linalg.norm(z_before - z_or) <= 1e-12 * np.linalg.norm(z_or)
+    S.close()
+
+
+def test_failed_rebuild_keeps_previous_operator(sequence):
+    """A singular diagonal block makes the rebuilding solve fail; the handle
+    keeps its previous B (inspection calls work and give the same bits), and
+    the next valid values solve normally."""
+    from paper_2201_01970_amd import CprError, Params, Solver
+    from paper_2201_01970_amd import _capi as capi
+
+    (c0, b0), (c1, b1) = sequence[0], sequence[1]
+    S = Solver(_dev(c0.row_ptr), _dev(c0.col), _dev(c0.vals.reshape(-1)), Params(reuse_mode=0))
+    v = _dev(bo.rhs(c0.ndof, 92))
+    z0 = S.precond(v).cpu().numpy()
+    bad = c1.vals.copy()
+    d0 = int(np.nonzero(c1.col[c1.row_ptr[5]:c1.row_ptr[6]] == 5)[0][0]) + int(c1.row_ptr[5])
+    bad[d0] = 0.0
+    S.update_values(_dev(bad.reshape(-1)))
+    with pytest.raises(CprError) as e:
+        S.solve(_dev(b1), tol=1e-6)
+    assert e.value.status == capi.CPR_ERR_SINGULAR_BLOCK
+    assert np.array_equal(S.precond(v).cpu().numpy(), z0)
+    S.update_values(_dev(c1.vals.reshape(-1)))
+    x, info = S.solve(_dev(b1), tol=1e-6)
+    assert info["rebuilt"] == 1 and info["relres_true"] < 1e-6
+    S.close()

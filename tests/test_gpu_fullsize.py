@@ -14,8 +14,16 @@ configuration the benchmark times, checked where the oracle can follow:
   classes independent in S and S^T; every F point with strong dependencies
   has a strong C dependency; level sizes shrink;
 * both solves reach true relres < 1e-6 (recomputed with the oracle's block
-  residual) with iteration counts within 10% of each other.
+  residual) with iteration counts within 10% of each other;
+* against the oracle's own solve at this size (stored by
+  tests/golden/make_fullsize_golden.py, which runs only the oracle): the FP64
+  path takes the oracle's iteration count and its iterate matches on 20000
+  seeded sampled unknowns and in norm within 1e-10 relative; the FP32 path is
+  within 10% of the oracle's iterations (FP64 and float32 model).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -181,3 +189,42 @@ def test_fullsize_solves(big):
         its[fp32] = info["iterations"]
         S.close()
     assert abs(its[True] - its[False]) <= max(1, 0.1 * its[False])
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(which):
+    with open(os.path.join(GOLDEN, f"oracle_fullsize_{which}.json")) as f:
+        return json.load(f)
+
+
+def _check_against_golden(case, b, g, tag):
+    from paper_2201_01970_amd import Params, Solver
+
+    assert g["n_b"] == case.n_b and g["nnz_b"] == case.nnz_b
+    idx = np.asarray(g["fp64"]["sample_dof"], dtype=np.int64)
+    gx = np.asarray(g["fp64"]["sample_x"])
+    for fp32 in (False, True):
+        S = Solver(_dev(case.row_ptr), _dev(case.col), _dev(case.vals.reshape(-1)), Params(precond_fp32=fp32))
+        x, info = S.solve(_dev(b), tol=1e-6)
+        x = x.cpu().numpy()
+        S.close()
+        d = np.linalg.norm(x[idx] - gx) / np.linalg.norm(gx)
+        dn = abs(np.linalg.norm(x) - g["fp64"]["x_norm"]) / g["fp64"]["x_norm"]
+        print(f"[{tag}] fp32={fp32} gpu its={info['iterations']} relres={info['relres_true']:.3e} | oracle fp64 "
+              f"its={g['fp64']['iterations']} relres={g['fp64']['relres_true']:.3e}, float32 model "
+              f"its={g['fp32_model']['iterations']} | sampled x diff {d:.2e}, norm diff {dn:.2e}", flush=True)
+        assert info["relres_true"] < 1e-6
+        if not fp32:
+            assert info["iterations"] == g["fp64"]["iterations"]
+            assert d <= 1e-10 and dn <= 1e-10
+            assert abs(info["relres_true"] - g["fp64"]["relres_true"]) <= 1e-2 * g["fp64"]["relres_true"]
+        else:
+            for ref in (g["fp64"]["iterations"], g["fp32_model"]["iterations"]):
+                assert abs(info["iterations"] - ref) <= max(1, 0.1 * ref)
+
+
+def test_fullsize_solve_matches_oracle_golden(big):
+    case, b = big
+    _check_against_golden(case, b, _golden("spe10"), "fullsize vs oracle")

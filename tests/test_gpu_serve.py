@@ -5,13 +5,18 @@
   repeat Newton steps reusing the resident hierarchy.
 * Results equal those of a plain handle with the same parameters and agree
   with the true residual.
+* Every served request matches the oracle: each case's request stream is the
+  oracle's Newton sequence (Algorithm "ASCPR", relative rule 1.3, float32
+  preconditioner model): same rebuild decisions, same iteration counts,
+  iterate within 1e-8 relative (the bar of the single-solve FP32 parity
+  test; the float32 and float64 preconditioner models differ by about 3e-9).
 * A budget smaller than one case rejects the request (CPR_ERR_OOM); a budget
   for about one case evicts idle cases and still serves everything.
 """
 import numpy as np
 import pytest
 
-from oracle import cpr
+from oracle import ascpr, cpr
 from workloads import blackoil as bo
 
 pytestmark = pytest.mark.gpu
@@ -95,3 +100,24 @@ def test_budget_rejection_and_eviction():
     for (cid, c, b), (x, info) in zip(reqs, res):
         rel = np.linalg.norm(cpr.bsr_residual(cpr.Bsr.from_case(c), x, b)) / np.linalg.norm(b)
         assert rel < 1e-6
+
+
+def test_served_requests_match_oracle():
+    reqs = _requests()
+    served, stats = _run(reqs, slots=4)
+    assert stats["evictions"] == 0
+    for cid in sorted({r[0] for r in reqs}):
+        idx = [k for k, r in enumerate(reqs) if r[0] == cid]
+        steps = [(cpr.Bsr.from_case(reqs[k][1]), reqs[k][2]) for k in idx]
+        reps = ascpr.solve_sequence(steps, mode="factor", factor=1.3, dtype=np.float32)
+        for n, (k, rep) in enumerate(zip(idx, reps)):
+            x, info = served[k]
+            d = np.linalg.norm(x - rep.x) / np.linalg.norm(rep.x)
+            print(f"[serve vs oracle] case {cid} request {k}: gpu its={info['iterations']} "
+                  f"rebuilt={info['rebuilt']} | oracle its={rep.iterations} rebuilt={rep.rebuilt} | "
+                  f"diff {d:.2e}", flush=True)
+            assert info["status"] == "CPR_OK"
+            assert info["iterations"] == rep.iterations, (cid, k)
+            if n > 0:
+                assert bool(info["rebuilt"]) == rep.rebuilt, (cid, k)
+            assert d <= 1e-8, (cid, k)
