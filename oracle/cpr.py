@@ -24,6 +24,10 @@ preconditioner):
   D_i^{-1} the inverse of the diagonal block (LU with partial pivoting).
 * Block products y_i[r] = sum over blocks in stored order of
   a[r][0]*x0 + a[r][1]*x1 + a[r][2]*x2, added one product at a time.
+* ``second_stage="bilu"`` replaces the block-GS sweep by the paper's own R:
+  block ILU(0) of A in natural order, applied with level-scheduled
+  triangular solves (module ``bilu``).  Its factors are SETUP products, so
+  they stay frozen with the rest of B when B is reused.
 """
 from __future__ import annotations
 
@@ -31,7 +35,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import amg, coloring
+from . import amg, bilu, coloring
 from .sparse import Csr
 
 
@@ -170,6 +174,8 @@ class CprPreconditioner:
     block_colours: list
     Dinv: np.ndarray
     dtype: type = np.float64
+    bilu: bilu.BiluFactors | None = None  # set when the second stage is block ILU(0)
+    bilu_levels: tuple | None = None      # (forward, backward) level of every row
 
     def apply(self, v):
         """z = B v (Algorithm CPR method with x = 0)."""
@@ -180,12 +186,26 @@ class CprPreconditioner:
         z = prolong_pressure(e.astype(dt))
         Ad = self.A if dt == np.float64 else Bsr(self.A.row_ptr, self.A.col, self.A.vals.astype(dt))
         r = bsr_residual(Ad, z, v)
-        z = z + block_gs(Ad, self.block_colours, self.Dinv, r)
+        if self.bilu is not None:
+            F = self.bilu if dt == np.float64 else self.bilu.cast(dt)
+            z = z + bilu.solve_by_levels(F, r, *self.bilu_levels)
+        else:
+            z = z + block_gs(Ad, self.block_colours, self.Dinv, r)
         return z
 
 
-def setup(A: Bsr, params: amg.AmgParams | None = None, dtype=np.float64) -> CprPreconditioner:
+def setup(A: Bsr, params: amg.AmgParams | None = None, dtype=np.float64,
+          second_stage: str = "bgs") -> CprPreconditioner:
+    """SETUP of B.  second_stage: "bgs" (multi-colour block Gauss-Seidel) or
+    "bilu" (block ILU(0) with level-scheduled solves)."""
     H = amg.build_hierarchy(pressure_matrix(A), params)
+    Af = Bsr(A.row_ptr.copy(), A.col.copy(), A.vals.copy())
+    if second_stage == "bilu":
+        F = bilu.bilu0(Af)
+        levels = (bilu.forward_levels(F.row_ptr, F.col), bilu.backward_levels(F.row_ptr, F.col))
+        return CprPreconditioner(A=Af, amg=H, block_colours=[], Dinv=F.Uinv, dtype=dtype, bilu=F,
+                                 bilu_levels=levels)
+    if second_stage != "bgs":
+        raise ValueError(second_stage)
     colours = coloring.vertices_grouping(A.n_b, block_graph(A))
-    return CprPreconditioner(A=Bsr(A.row_ptr.copy(), A.col.copy(), A.vals.copy()), amg=H,
-                             block_colours=colours, Dinv=diag_inverses(A), dtype=dtype)
+    return CprPreconditioner(A=Af, amg=H, block_colours=colours, Dinv=diag_inverses(A), dtype=dtype)
