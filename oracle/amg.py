@@ -20,6 +20,15 @@
   forward.  Per row: s = b_i, then s = s - a_ij*x_j for every stored j != i
   in stored order, then x_i = s / a_ii.
 
+* PGS-NO (the paper's reference smoother, "parallel GS based on natural
+  ordering", run on NT threads in Section 6): the rows in natural order are
+  split into ``gs_chunks`` contiguous chunks (sizes differing by at most one,
+  the longer ones first); inside a chunk the rows are relaxed in order with
+  the newest values of the chunk's own rows, and rows of other chunks are
+  read as they were when the sweep started (block Jacobi across chunks,
+  Gauss-Seidel inside them).  One chunk is classical forward GS; one row per
+  chunk is Jacobi.  Selected with ``smoother="pgs-no"``.
+
 * V-cycle from a zero initial guess: nu1 pre-sweeps, r = b - A x (stored
   order, diagonal included), b_c = R r (row sums from 0 in stored order),
   recursion, x_i = x_i + (sum_J p_iJ e_J) with the sum from 0 in stored
@@ -44,6 +53,8 @@ class AmgParams:
     max_levels: int = 25
     pre_sweeps: int = 2
     post_sweeps: int = 2
+    smoother: str = "pgs-scm"   # or "pgs-no"
+    gs_chunks: int = 4096       # PGS-NO: chunks per level
 
 
 @dataclass
@@ -118,6 +129,51 @@ def colour_sweep(A: Csr, colours, x, b, diag=None):
     return x
 
 
+def chunk_bounds(n, n_chunks):
+    """PGS-NO chunk boundaries: min(n_chunks, n) contiguous ranges of rows."""
+    c = max(1, min(int(n_chunks), n))
+    q, r = divmod(n, c)
+    bounds = [0]
+    for k in range(c):
+        bounds.append(bounds[-1] + q + (1 if k < r else 0))
+    return bounds
+
+
+def natural_chunk_sweep(A: Csr, n_chunks, x, b, diag=None):
+    """One PGS-NO sweep (in place on x).
+
+    Row t of every chunk is relaxed in the same step (chunks are independent
+    given the sweep-start snapshot, so this is the per-chunk sequential loop
+    run side by side).  Per row: s = b_i, then s = s - a_ij * xt_j for every
+    stored j != i in stored order, with xt_j = x_j when j is in the row's chunk
+    (already relaxed when j < i) and the snapshot otherwise; x_i = s / a_ii."""
+    if diag is None:
+        diag = A.diagonal()
+    n = A.n_rows
+    bounds = np.asarray(chunk_bounds(n, n_chunks), dtype=np.int64)
+    chunk = np.repeat(np.arange(len(bounds) - 1), np.diff(bounds))
+    snap = x.copy()
+    lo, hi = bounds[:-1], bounds[1:]
+    for t in range(int(np.max(hi - lo)) if n else 0):
+        rows = (lo + t)[lo + t < hi]
+        cols, vals, _ = padded(A, rows)
+        vals = np.where(cols == rows[:, None], 0.0, vals)
+        s = b[rows].astype(x.dtype, copy=True)
+        for k in range(cols.shape[1]):
+            c = cols[:, k]
+            xt = np.where(chunk[c] == chunk[rows], x[c], snap[c])
+            s = s - vals[:, k].astype(x.dtype) * xt
+        x[rows] = s / diag[rows].astype(x.dtype)
+    return x
+
+
+def smooth(H: Hierarchy, lev: Level, A: Csr, x, b):
+    """One smoothing sweep of the configured kind on level ``lev``."""
+    if H.params.smoother == "pgs-no":
+        return natural_chunk_sweep(A, H.params.gs_chunks, x, b, lev.diag)
+    return colour_sweep(A, lev.colours, x, b, lev.diag)
+
+
 def vcycle(H: Hierarchy, b, level=0, dtype=np.float64):
     """One V-cycle applied to b on ``level`` from a zero initial guess."""
     lev = H.levels[level]
@@ -129,7 +185,7 @@ def vcycle(H: Hierarchy, b, level=0, dtype=np.float64):
     x = np.zeros(A.n_rows, dtype=dtype)
     b = b.astype(dtype)
     for _ in range(p.pre_sweeps):
-        colour_sweep(A, lev.colours, x, b, lev.diag)
+        smooth(H, lev, A, x, b)
     r = residual(A, x, b)
     R = lev.R if dtype == np.float64 else _cast(lev.R, dtype)
     P = lev.P if dtype == np.float64 else _cast(lev.P, dtype)
@@ -137,7 +193,7 @@ def vcycle(H: Hierarchy, b, level=0, dtype=np.float64):
     e = vcycle(H, bc, level + 1, dtype)
     x = x + matvec(P, e)
     for _ in range(p.post_sweeps):
-        colour_sweep(A, lev.colours, x, b, lev.diag)
+        smooth(H, lev, A, x, b)
     return x
 
 
