@@ -49,7 +49,7 @@ class StepReport:
 
 
 def solve_sequence(steps, params: AmgParams | None = None, tol=1e-6, m=30, mode="factor",
-                   mu=0, factor=1.3, dtype=np.float64, second_stage="bgs"):
+                   mu=0, factor=1.3, dtype=np.float64, second_stage="bgs", decoupling="none"):
     """Run ASCPR-FGMRES over an iterable of (A: cpr.Bsr, b) pairs."""
     B = None
     it_prev = it_ref = 0
@@ -58,7 +58,7 @@ def solve_sequence(steps, params: AmgParams | None = None, tol=1e-6, m=30, mode=
     for k, (A, b) in enumerate(steps, start=1):
         rebuild = decide_rebuild(k, it_prev, it_ref, mode, mu, factor, size_changed=(A.n_b != n_prev))
         if rebuild:
-            B = cpr.setup(A, params, dtype, second_stage=second_stage)
+            B = cpr.setup(A, params, dtype, second_stage=second_stage, decoupling=decoupling)
         res = fgmres.fgmres(lambda v, A=A: cpr.bsr_matvec(A, v), B.apply, b, tol=tol, m=m)
         it_prev = res.iterations
         if rebuild:

@@ -24,6 +24,15 @@ preconditioner):
   D_i^{-1} the inverse of the diagonal block (LU with partial pivoting).
 * Block products y_i[r] = sum over blocks in stored order of
   a[r][0]*x0 + a[r][1]*x1 + a[r][2]*x2, added one product at a time.
+* ``decoupling`` (the survey's next step beyond the paper, which leaves the
+  well and decoupling details out): a block-diagonal W is applied to the
+  rows before anything else, and B is built on W A: "quasi-impes" takes
+  W_i = I with (0,1) = -D_01/D_11 and (0,2) = -D_02/D_22 (the pressure row
+  loses the saturation derivatives of its own diagonal block, using diagonal
+  entries only); "abf" (alternate block factorisation) takes W_i = D_i^{-1},
+  so W A has identity diagonal blocks.  The preconditioner for A is then
+  v -> B_{WA}(W v); the outer FGMRES still works on A.  W is a SETUP product
+  (frozen with B).
 * ``second_stage="bilu"`` replaces the block-GS sweep by the paper's own R:
   block ILU(0) of A in natural order, applied with level-scheduled
   triangular solves (module ``bilu``).  Its factors are SETUP products, so
@@ -165,6 +174,47 @@ def block_gs(A: Bsr, colours, Dinv, r):
     return d.reshape(-1)
 
 
+def decoupling_weights(A: Bsr, kind):
+    """W_i per cell for the decoupling ``kind`` ("quasi-impes" or "abf")."""
+    D = np.empty((A.n_b, 3, 3))
+    for i in range(A.n_b):
+        a, b = A.row_ptr[i], A.row_ptr[i + 1]
+        hit = np.nonzero(A.col[a:b] == i)[0]
+        D[i] = A.vals[a + hit[0]]
+    if kind == "abf":
+        return np.linalg.inv(D)
+    if kind == "quasi-impes":
+        W = np.zeros_like(D)
+        W[:, 0, 0] = W[:, 1, 1] = W[:, 2, 2] = 1.0
+        W[:, 0, 1] = -D[:, 0, 1] / D[:, 1, 1]
+        W[:, 0, 2] = -D[:, 0, 2] / D[:, 2, 2]
+        return W
+    raise ValueError(kind)
+
+
+def left_blocks(W, A: Bsr) -> Bsr:
+    """W A: every stored block of row i multiplied on the left by W_i, each
+    entry sum_m W[r][m] A[m][c] taken from 0 over m = 0, 1, 2."""
+    rows = np.repeat(np.arange(A.n_b), np.diff(A.row_ptr))
+    Wr = W[rows]
+    out = np.zeros_like(A.vals)
+    for r in range(3):
+        for c in range(3):
+            for m in range(3):
+                out[:, r, c] = out[:, r, c] + Wr[:, r, m] * A.vals[:, m, c]
+    return Bsr(A.row_ptr.copy(), A.col.copy(), out)
+
+
+def block_gemv(W, v):
+    """(W v)_i = W_i v_i, each component summed from 0 over columns 0, 1, 2."""
+    v3 = v.reshape(-1, 3)
+    out = np.zeros_like(v3)
+    for r in range(3):
+        for c in range(3):
+            out[:, r] = out[:, r] + W[:, r, c] * v3[:, c]
+    return out.reshape(-1)
+
+
 @dataclass
 class CprPreconditioner:
     """Everything SETUP produces (frozen while it is reused)."""
@@ -176,11 +226,14 @@ class CprPreconditioner:
     dtype: type = np.float64
     bilu: bilu.BiluFactors | None = None  # set when the second stage is block ILU(0)
     bilu_levels: tuple | None = None      # (forward, backward) level of every row
+    W: np.ndarray | None = None           # decoupling weights (B is built on W A)
 
     def apply(self, v):
         """z = B v (Algorithm CPR method with x = 0)."""
         dt = self.dtype
         v = v.astype(dt)
+        if self.W is not None:
+            v = block_gemv(self.W.astype(dt), v)
         rp = restrict_pressure(v)
         e = amg.vcycle(self.amg, rp, 0, dt)
         z = prolong_pressure(e.astype(dt))
@@ -195,17 +248,22 @@ class CprPreconditioner:
 
 
 def setup(A: Bsr, params: amg.AmgParams | None = None, dtype=np.float64,
-          second_stage: str = "bgs") -> CprPreconditioner:
+          second_stage: str = "bgs", decoupling: str = "none") -> CprPreconditioner:
     """SETUP of B.  second_stage: "bgs" (multi-colour block Gauss-Seidel) or
-    "bilu" (block ILU(0) with level-scheduled solves)."""
+    "bilu" (block ILU(0) with level-scheduled solves); decoupling: "none",
+    "quasi-impes" or "abf" (B is then built on W A and applied to W v)."""
+    W = None
+    if decoupling != "none":
+        W = decoupling_weights(A, decoupling)
+        A = left_blocks(W, A)
     H = amg.build_hierarchy(pressure_matrix(A), params)
     Af = Bsr(A.row_ptr.copy(), A.col.copy(), A.vals.copy())
     if second_stage == "bilu":
         F = bilu.bilu0(Af)
         levels = (bilu.forward_levels(F.row_ptr, F.col), bilu.backward_levels(F.row_ptr, F.col))
         return CprPreconditioner(A=Af, amg=H, block_colours=[], Dinv=F.Uinv, dtype=dtype, bilu=F,
-                                 bilu_levels=levels)
+                                 bilu_levels=levels, W=W)
     if second_stage != "bgs":
         raise ValueError(second_stage)
     colours = coloring.vertices_grouping(A.n_b, block_graph(A))
-    return CprPreconditioner(A=Af, amg=H, block_colours=colours, Dinv=diag_inverses(A), dtype=dtype)
+    return CprPreconditioner(A=Af, amg=H, block_colours=colours, Dinv=diag_inverses(A), dtype=dtype, W=W)

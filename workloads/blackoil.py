@@ -217,6 +217,88 @@ def assemble(shape, active, faces: FaceData, poro=PORO, compress=COMPRESS) -> Bs
                    grid=shape, active=active)
 
 
+def add_wells(case: BsrCase, columns, seed, well_index=5.0, frac_hi=0.5, u=U_COUPLING) -> BsrCase:
+    """Append implicit wells to a reservoir Jacobian: the [A_RR A_RW; A_WR A_WW]
+    system of the paper's Section 2.2, one bottom-hole-pressure unknown per
+    well, each well stored as an extra 3x3 block row after the cells so the
+    matrix stays 3x3-block (slots 1 and 2 of a well are placeholder unknowns
+    with identity equations).
+
+    A well perforates every active cell of a vertical grid column (ix, iy);
+    the columns must be distinct.  Its productivity at cell c is PI_c =
+    well_index * (mean transmissibility of c's faces).  Cell c gains the
+    block A_cw with column 0 = -PI_c * (1, f1, f2), f_a ~ U[0, frac_hi], and
+    the matching diagonal terms (D[0][0] += PI_c, D[a][0] += PI_c f_a, and
+    D[a][a] += PI_c f_a so the saturation rows stay dominant); the well row
+    has A_wc[0, :] = -PI_c * (1, u1, u2), u ~ U[-u, u], and A_ww =
+    diag(sum_c PI_c, 1, 1) (a rate-controlled well equation).  Random draws
+    are taken well by well, perforation by perforation (f1, f2, u1, u2)."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = case.grid
+    n_b = case.n_b
+    rp = case.row_ptr.astype(np.int64)
+    col = case.col.astype(np.int64)
+    act_idx = np.full(nx * ny * nz, -1, dtype=np.int64)
+    act_idx[np.nonzero(case.active)[0]] = np.arange(n_b)
+    rowlen = np.diff(rp)
+    row_of = np.repeat(np.arange(n_b), rowlen)
+    offd = col != row_of
+    mean_t = np.bincount(row_of[offd], weights=-case.vals[offd, 0, 0], minlength=n_b) / np.maximum(rowlen - 1, 1)
+    diag_pos = np.nonzero(~offd)[0]  # one diagonal block per row, in row order
+    perfs = []
+    for ix, iy in columns:
+        cells = act_idx[ix + nx * (iy + ny * np.arange(nz))]
+        perfs.append(cells[cells >= 0])
+    all_cells = np.concatenate(perfs) if perfs else np.zeros(0, dtype=np.int64)
+    if np.unique(all_cells).size != all_cells.size:
+        raise ValueError("well columns must be distinct")
+    n_w = len(perfs)
+    extra = np.zeros(n_b, dtype=np.int64)
+    extra[all_cells] = 1
+    # new layout: the cell rows (old entries, then the well entry), then the well rows
+    new_len = np.concatenate([rowlen + extra, [p.size + 1 for p in perfs]]).astype(np.int64)
+    new_rp = np.zeros(n_b + n_w + 1, dtype=np.int64)
+    np.cumsum(new_len, out=new_rp[1:])
+    new_col = np.empty(new_rp[-1], dtype=np.int64)
+    new_vals = np.zeros((new_rp[-1], 3, 3))
+    old_pos = new_rp[row_of] + (np.arange(rp[-1]) - rp[row_of])
+    new_col[old_pos] = col
+    new_vals[old_pos] = case.vals
+    for w, cells in enumerate(perfs):
+        wi = n_b + w
+        draws = rng.uniform(size=(cells.size, 4))
+        f = frac_hi * draws[:, :2]
+        uu = u * (2.0 * draws[:, 2:] - 1.0)
+        pi = well_index * mean_t[cells]
+        pos = new_rp[cells] + rowlen[cells]  # the last entry of each perforated row
+        new_col[pos] = wi
+        new_vals[pos, 0, 0] = -pi
+        new_vals[pos, 1, 0] = -pi * f[:, 0]
+        new_vals[pos, 2, 0] = -pi * f[:, 1]
+        dp = old_pos[diag_pos[cells]]
+        new_vals[dp, 0, 0] += pi
+        new_vals[dp, 1, 0] += pi * f[:, 0]
+        new_vals[dp, 2, 0] += pi * f[:, 1]
+        new_vals[dp, 1, 1] += pi * f[:, 0]
+        new_vals[dp, 2, 2] += pi * f[:, 1]
+        base = new_rp[wi]
+        new_col[base:base + cells.size] = cells
+        new_vals[base:base + cells.size, 0, 0] = -pi
+        new_vals[base:base + cells.size, 0, 1] = -pi * uu[:, 0]
+        new_vals[base:base + cells.size, 0, 2] = -pi * uu[:, 1]
+        new_col[base + cells.size] = wi
+        new_vals[base + cells.size] = np.diag([pi.sum(), 1.0, 1.0])
+    return BsrCase(row_ptr=new_rp.astype(np.int32), col=new_col.astype(np.int32), vals=new_vals, grid=case.grid,
+                   active=case.active, meta=dict(case.meta, wells=[tuple(c) for c in columns]))
+
+
+def five_spot(shape):
+    """Well columns of a five-spot pattern: four corners (one cell in from the
+    edges) and the centre."""
+    nx, ny, _ = shape
+    return [(1, 1), (nx - 2, 1), (1, ny - 2), (nx - 2, ny - 2), (nx // 2, ny // 2)]
+
+
 def rhs(n_dof, seed):
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=n_dof)
 
