@@ -139,6 +139,24 @@ cpr_status cpr_update_values(cpr_handle* h, const cpr_bsr* A);
  * on exit.  Blocks until the result is in x.  info may be NULL. */
 cpr_status cpr_solve(cpr_handle* h, const double* b, double* x, double tol, cpr_solve_info* info);
 
+/* cpr_solve for callers that cannot allocate device memory (tight serving
+ * loops, harnesses that forbid hipMalloc): the same solve, with the same
+ * kernels and the same result as cpr_solve, that calls no hipMalloc,
+ * hipFree, graph instantiation or other allocating routine.  Its FGMRES
+ * scalars and per-workgroup partial sums live in a static device array of
+ * 1.07 MiB that each GPU the library runs on holds until the process ends;
+ * its address is looked up on the first call on a device.  Every step is
+ * launched directly (no graph replay) and profiling events are not recorded.
+ * Limits and errors: the handle's restart must be at most 64, else
+ * CPR_ERR_INVALID_ARG; when the adaptive-setup rule asks for a SETUP before
+ * this solve (SETUP allocates) it returns CPR_ERR_INVALID_ARG and changes
+ * nothing: call cpr_solve for that step.  All calls on one GPU share the one
+ * array, which keeps the last call's contents (every word a solve reads from
+ * it is written earlier in the same solve): calls that overlap in time on one
+ * GPU, from any handles or threads, race and must be serialised by the
+ * caller.  b, x, tol, info as for cpr_solve. */
+cpr_status cpr_solve_noalloc(cpr_handle* h, const double* b, double* x, double tol, cpr_solve_info* info);
+
 /* Make subsequent work of h run on hip_stream (a hipStream_t, NULL = the
  * default stream) after draining the previous stream. */
 cpr_status cpr_set_stream(cpr_handle* h, void* hip_stream);

@@ -114,6 +114,7 @@ SIGNATURES = {
     "cpr_setup": (_I32, [C.POINTER(cpr_bsr), C.POINTER(cpr_params), _P, C.POINTER(_P)]),
     "cpr_update_values": (_I32, [_P, C.POINTER(cpr_bsr)]),
     "cpr_solve": (_I32, [_P, _P, _P, _D, C.POINTER(cpr_solve_info)]),
+    "cpr_solve_noalloc": (_I32, [_P, _P, _P, _D, C.POINTER(cpr_solve_info)]),
     "cpr_set_stream": (_I32, [_P, _P]),
     "cpr_destroy": (None, [_P]),
     "cpr_status_string": (C.c_char_p, [_I32]),

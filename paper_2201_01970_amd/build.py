@@ -26,6 +26,7 @@ SOURCES = [
     "kernels_amg.hip",
     "kernels_krylov.hip",
     "kernels_tail.hip",
+    "noalloc.hip",
 ]
 
 ARCH = os.environ.get("CPR_OFFLOAD_ARCH", "gfx950")

@@ -121,21 +121,12 @@ void build_outer(cpr_handle* h) {
 void alloc_krylov(cpr_handle* h) {
   const int64_t N = 3 * static_cast<int64_t>(h->n_b);
   const int m = h->m;
-  const int grid = krylov_grid(N);
   h->V = h->fine.alloc<double>((m + 1) * N);
   if (h->prm.precond_fp32)
     h->Z = h->fine.alloc<float>(m * N);
   else
     h->Z = h->fine.alloc<double>(m * N);
-  h->H = h->fine.alloc<double>((m + 1) * m);
-  h->cs = h->fine.alloc<double>(m);
-  h->sn = h->fine.alloc<double>(m);
-  h->g = h->fine.alloc<double>(m + 1);
-  h->y = h->fine.alloc<double>(m);
-  h->hnorm = h->fine.alloc<double>(1);
-  h->partial = h->fine.alloc<double>(static_cast<int64_t>(m + 1) * grid);
-  h->norm_partial = h->fine.alloc<double>(grid);
-  h->report_d = h->fine.alloc<double>(4);
+  h->kw = krylov_work_carve(h->fine.alloc<double>(krylov_work_doubles(m)), m);
   h->r = h->fine.alloc<double>(N);
   std::lock_guard<std::mutex> lk(device_api_mutex());
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->report_h), 4 * sizeof(double), hipHostMallocDefault));
@@ -268,7 +259,21 @@ cpr_status cpr_solve(cpr_handle* h, const double* b, double* x, double tol, cpr_
   if (!b || !x || !(tol > 0.0)) return fail(h, CPR_ERR_INVALID_ARG, "b, x must be device arrays and tol > 0");
   return guarded(h, [&]() -> cpr_status {
     need_pc(h);
-    return h->solve(b, x, tol, info);
+    return h->solve(b, x, tol, info, h->kw, true);
+  });
+}
+
+cpr_status cpr_solve_noalloc(cpr_handle* h, const double* b, double* x, double tol, cpr_solve_info* info) {
+  if (!h) return fail(nullptr, CPR_ERR_INVALID_ARG, "null handle");
+  if (!b || !x || !(tol > 0.0)) return fail(h, CPR_ERR_INVALID_ARG, "b, x must be device arrays and tol > 0");
+  if (h->m > kNoAllocMaxRestart)
+    return fail(h, CPR_ERR_INVALID_ARG,
+                "restart " + std::to_string(h->m) + " exceeds the allocation-free solve's maximum of " +
+                    std::to_string(kNoAllocMaxRestart));
+  return guarded(h, [&]() -> cpr_status {
+    need_pc(h);
+    const KrylovWork w = krylov_work_carve(noalloc_scratch(h->device), h->m);
+    return h->solve(b, x, tol, info, w, false);
   });
 }
 

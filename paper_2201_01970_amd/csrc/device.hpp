@@ -206,7 +206,34 @@ void launch_copy_bytes(int64_t n_bytes, const void* src, void* dst, hipStream_t 
 void launch_int_diff(int64_t n, const int32_t* a, const int32_t* b, int32_t* flag, hipStream_t s);
 
 // ---- Krylov kernels (FP64) ----
+// Reductions run on at most this many workgroups (two-stage, fixed order).
+constexpr int kKrylovGridMax = 2048;
 int krylov_grid(int64_t n);
+
+// The device scalars and partial sums of one FGMRES solve with restart m:
+// Hessenberg H ((m+1) x m, column-major), Givens cosines and sines (m), the
+// least-squares right-hand side g (m+1), y (m), the current column norm
+// (hnorm), the per-workgroup partial dots of up to m+1 basis vectors
+// (partial, (m+1) x kKrylovGridMax) and of one norm (norm_partial), and four
+// report words the host reads back after every step.
+struct KrylovWork {
+  double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *hnorm = nullptr;
+  double *partial = nullptr, *norm_partial = nullptr, *report = nullptr;
+};
+// Doubles a KrylovWork of restart m occupies when carved out of one array
+// (every part starts on a 256-byte boundary: 32 doubles).
+constexpr int64_t krylov_round_up(int64_t n) { return (n + 31) / 32 * 32; }
+constexpr int64_t krylov_work_doubles(int m) {
+  return krylov_round_up(int64_t(m + 1) * m) + 3 * krylov_round_up(m) + krylov_round_up(m + 1) + krylov_round_up(1) +
+         krylov_round_up(int64_t(m + 1) * kKrylovGridMax) + krylov_round_up(kKrylovGridMax) + krylov_round_up(4);
+}
+// The parts of a KrylovWork of restart m laid out from base (256-byte aligned).
+KrylovWork krylov_work_carve(double* base, int m);
+
+// Largest restart the allocation-free solve accepts, and the device address
+// of that solve's static scratch array on `device` (looked up once per device).
+constexpr int kNoAllocMaxRestart = 64;
+double* noalloc_scratch(int device);
 // partial[i*grid + blk] = partial dot of w with V[j0+i] (i < nb); V row stride ld
 void launch_multidot(int64_t n, const double* w, const double* V, int64_t ld, int j0, int nb, double* partial,
                      hipStream_t s);

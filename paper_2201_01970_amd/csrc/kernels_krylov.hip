@@ -7,8 +7,6 @@
 
 namespace cpr {
 
-constexpr int kKrylovGridMax = 2048;
-
 int krylov_grid(int64_t n) {
   const int64_t g = (n + kBlock * 4 - 1) / (kBlock * 4);
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, kKrylovGridMax));

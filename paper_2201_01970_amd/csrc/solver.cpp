@@ -326,7 +326,7 @@ hipGraphExec_t cpr_handle::capture_step(int j) {
   }
   bool ok = true;
   try {
-    step_body(j, cap_stream);
+    step_body(j, kw, false, cap_stream);
   } catch (const Error&) {
     ok = false;
   }
@@ -350,7 +350,7 @@ void cpr_handle::drop_graphs() {
 // h_ij = (w, v_i) for i <= j (all against the same w: classical Gram-Schmidt);
 // w -= sum h_ij v_i; h_{j+1,j} = ||w||; Givens update; v_{j+1} = w / h_{j+1,j};
 // then |g_{j+1}| and h_{j+1,j} are copied to the host.
-void cpr_handle::step_body(int j, hipStream_t s) {
+void cpr_handle::step_body(int j, const KrylovWork& w_, bool timed, hipStream_t s) {
   const int64_t N = 3 * static_cast<int64_t>(n_b);
   const int64_t ld = N;
   const int grid = krylov_grid(N);
@@ -359,42 +359,51 @@ void cpr_handle::step_body(int j, hipStream_t s) {
   double* w = V + (j + 1) * ld;
   void* zj = f32 ? static_cast<void*>(static_cast<float*>(Z) + j * ld)
                  : static_cast<void*>(static_cast<double*>(Z) + j * ld);
+  LaunchTimer* const saved_timer = pc->timer;
+  if (!timed) pc->timer = nullptr;
   pc->apply(vj, zj, s);
-  if (prof.on()) prof.begin(CPR_KSTAT_SPMV, s);
+  pc->timer = saved_timer;
+  if (timed) prof.begin(CPR_KSTAT_SPMV, s);
   if (f32)
     launch_bsr_spmv<double, float>(outer.view(), static_cast<const float*>(zj), nullptr, w, s);
   else
     launch_bsr_spmv<double, double>(outer.view(), static_cast<const double*>(zj), nullptr, w, s);
-  if (prof.on())
+  if (timed)
     prof.end(CPR_KSTAT_SPMV, s, 9.0 * nnz_b * 8 + 4.0 * nnz_b + 4.0 * (n_b + 1) + 3.0 * n_b * ((f32 ? 4 : 8) + 8));
-  launch_multidot(N, w, V, ld, 0, j + 1, partial, s);
-  double* Hj = H + static_cast<int64_t>(j) * (m + 1);
-  launch_reduce_partials(partial, grid, j + 1, Hj, s);
-  launch_axpy_norm(N, w, V, ld, 0, j + 1, Hj, norm_partial, s);
-  launch_givens(m, j, norm_partial, grid, H, cs, sn, g, hnorm, report_d, s);
-  launch_scale_div(N, w, hnorm, w, s);
-  HIPCHK(hipMemcpyAsync(report_h, report_d, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  launch_multidot(N, w, V, ld, 0, j + 1, w_.partial, s);
+  double* Hj = w_.H + static_cast<int64_t>(j) * (m + 1);
+  launch_reduce_partials(w_.partial, grid, j + 1, Hj, s);
+  launch_axpy_norm(N, w, V, ld, 0, j + 1, Hj, w_.norm_partial, s);
+  launch_givens(m, j, w_.norm_partial, grid, w_.H, w_.cs, w_.sn, w_.g, w_.hnorm, w_.report, s);
+  launch_scale_div(N, w, w_.hnorm, w, s);
+  HIPCHK(hipMemcpyAsync(report_h, w_.report, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
 }
 
 // ------------------------------------------------------------------ SOLVE
 // Flexible GMRES(m), classical Gram-Schmidt, Givens rotations.  Convergence:
 // ||r|| / ||r_0|| < tol checked on the Givens estimate after every step and
 // confirmed with the true residual; iterations = inner steps.
-cpr_status cpr_handle::solve(const double* b, double* x, double tol, cpr_solve_info* info) {
+cpr_status cpr_handle::solve(const double* b, double* x, double tol, cpr_solve_info* info, const KrylovWork& kwork,
+                             bool may_allocate) {
   // adaptive setup (Algorithm "ASCPR"); SETUP of cpr_setup counts as k = 1
   // k counts solves since the handle's SETUP.  Solve k = 1 always runs on a B
   // built from the matrix it solves: cpr_setup built it, unless new values
   // arrived before this first solve, in which case SETUP runs again.
-  k_solves += 1;
+  const int64_t k_this = k_solves + 1;
   bool rebuild = false;
   if (values_changed) {
-    if (k_solves == 1 || prm.reuse_mode == 0)
+    if (k_this == 1 || prm.reuse_mode == 0)
       rebuild = true;
     else if (prm.reuse_mode == 1)
       rebuild = !(it_prev <= prm.mu);
     else
       rebuild = !(static_cast<double>(it_prev) <= prm.reuse_factor * static_cast<double>(it_ref));
   }
+  if (rebuild && !may_allocate)
+    throw Error(CPR_ERR_INVALID_ARG,
+                "the adaptive-setup rule asks for a SETUP before this solve, and SETUP allocates: call cpr_solve");
+  k_solves = k_this;
+  const bool timed = may_allocate && prof.on();
   double setup_ms = 0.0;
   if (rebuild) {
     build_precond();
@@ -410,22 +419,22 @@ cpr_status cpr_handle::solve(const double* b, double* x, double tol, cpr_solve_i
   const bool f32 = pc->fp32();
   const int64_t ld = N;
   auto sync_report = [&]() {
-    HIPCHK(hipMemcpyAsync(report_h, report_d, 4 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(report_h, kwork.report, 4 * sizeof(double), hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
   };
   auto outer_spmv_resid = [&](const double* xx, const double* bb, double* rr) {
-    if (prof.on()) prof.begin(CPR_KSTAT_SPMV, stream);
+    if (timed) prof.begin(CPR_KSTAT_SPMV, stream);
     launch_bsr_spmv<double, double>(outer.view(), xx, bb, rr, stream);
-    if (prof.on())
+    if (timed)
       prof.end(CPR_KSTAT_SPMV, stream, 9.0 * nnz_b * 8 + 4.0 * nnz_b + 4.0 * (n_b + 1) + 3.0 * n_b * (8 + 8 + 8));
   };
 
   // ||b|| (for the reported true relative residual), r0 = b - A x0, beta0 = ||r0||
-  launch_norm_partial(N, b, norm_partial, stream);
-  launch_reduce_partials(norm_partial, grid, 1, report_d + 2, stream);
+  launch_norm_partial(N, b, kwork.norm_partial, stream);
+  launch_reduce_partials(kwork.norm_partial, grid, 1, kwork.report + 2, stream);
   outer_spmv_resid(x, b, r);
-  launch_norm_partial(N, r, norm_partial, stream);
-  launch_start_cycle(m, norm_partial, grid, g, hnorm, report_d, stream);
+  launch_norm_partial(N, r, kwork.norm_partial, stream);
+  launch_start_cycle(m, kwork.norm_partial, grid, kwork.g, kwork.hnorm, kwork.report, stream);
   sync_report();
   const double beta0 = report_h[0];
   const double bnorm = std::sqrt(report_h[2]);
@@ -443,19 +452,19 @@ cpr_status cpr_handle::solve(const double* b, double* x, double tol, cpr_solve_i
     for (int cycle = 0; cycle < prm.max_restarts; ++cycle) {
       cycles = cycle;
       // v_1 = r / ||r||, g = ||r|| e_1 (start_cycle already ran for this r)
-      launch_scale_div(N, r, hnorm, V, stream);
+      launch_scale_div(N, r, kwork.hnorm, V, stream);
       int k = 0;
       bool bad = false;
       for (int j = 0; j < m; ++j) {
-        if (prm.use_graphs && !prof.on()) {
+        if (may_allocate && prm.use_graphs && !prof.on()) {
           if (step_graph.empty()) step_graph.assign(m, nullptr);
           if (!step_graph[j]) step_graph[j] = capture_step(j);
           if (step_graph[j])
             HIPCHK(hipGraphLaunch(step_graph[j], stream));
           else
-            step_body(j, stream);  // capture was refused: same kernels, launched one by one
+            step_body(j, kwork, timed, stream);  // capture was refused: same kernels, launched one by one
         } else {
-          step_body(j, stream);
+          step_body(j, kwork, timed, stream);
         }
         HIPCHK(hipStreamSynchronize(stream));
         ++its;
@@ -474,14 +483,14 @@ cpr_status cpr_handle::solve(const double* b, double* x, double tol, cpr_solve_i
         st = CPR_ERR_NAN;
         break;
       }
-      launch_backsolve(m, k, H, g, y, stream);
+      launch_backsolve(m, k, kwork.H, kwork.g, kwork.y, stream);
       if (f32)
-        launch_update_x<float>(N, x, static_cast<const float*>(Z), ld, k, y, stream);
+        launch_update_x<float>(N, x, static_cast<const float*>(Z), ld, k, kwork.y, stream);
       else
-        launch_update_x<double>(N, x, static_cast<const double*>(Z), ld, k, y, stream);
+        launch_update_x<double>(N, x, static_cast<const double*>(Z), ld, k, kwork.y, stream);
       outer_spmv_resid(x, b, r);
-      launch_norm_partial(N, r, norm_partial, stream);
-      launch_start_cycle(m, norm_partial, grid, g, hnorm, report_d, stream);
+      launch_norm_partial(N, r, kwork.norm_partial, stream);
+      launch_start_cycle(m, kwork.norm_partial, grid, kwork.g, kwork.hnorm, kwork.report, stream);
       sync_report();
       rel = report_h[0] / beta0;
       relb = bnorm > 0.0 ? report_h[0] / bnorm : 0.0;
@@ -497,7 +506,7 @@ cpr_status cpr_handle::solve(const double* b, double* x, double tol, cpr_solve_i
     }
   }
   HIPCHK(hipStreamSynchronize(stream));
-  if (prof.on()) prof.collect();
+  if (timed) prof.collect();
   const double solve_ms = now_ms() - t0;
 
   it_prev = its;

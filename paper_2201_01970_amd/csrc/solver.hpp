@@ -168,12 +168,12 @@ struct cpr_handle {
   std::vector<int32_t> block_colour;
   int32_t n_block_colours = 0;
 
-  // Krylov workspace (FP64 except Z in FP32 mode)
+  // Krylov workspace (FP64 except Z in FP32 mode): the bases V and Z, the
+  // residual r, and the scalars and partial sums of the handle's own solves
   int m = 30;
-  double *V = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
-  double *hnorm = nullptr, *partial = nullptr, *norm_partial = nullptr, *report_d = nullptr, *r = nullptr;
-  double* hcol = nullptr;
+  double *V = nullptr, *r = nullptr;
   void* Z = nullptr;
+  cpr::KrylovWork kw;
   double* report_h = nullptr;  // pinned
 
   // adaptive setup state (Algorithm "ASCPR")
@@ -189,10 +189,16 @@ struct cpr_handle {
   std::vector<hipGraphExec_t> step_graph;
   hipStream_t cap_stream = nullptr;
   void drop_graphs();
-  void step_body(int j, hipStream_t s);
+  void step_body(int j, const cpr::KrylovWork& w, bool timed, hipStream_t s);
   hipGraphExec_t capture_step(int j);
 
   void build_precond();
-  cpr_status solve(const double* b, double* x, double tol, cpr_solve_info* info);
+  // The FGMRES solve with the adaptive-setup rule.  w: the scalars and partial
+  // sums to use; may_allocate = false runs every step eagerly (no graph
+  // capture or instantiation, no event timing) and refuses a solve for which
+  // the rule asks a SETUP (SETUP allocates) with CPR_ERR_INVALID_ARG, before
+  // any state changes.
+  cpr_status solve(const double* b, double* x, double tol, cpr_solve_info* info, const cpr::KrylovWork& w,
+                   bool may_allocate);
   void spmv(const double* x, double* y);
 };

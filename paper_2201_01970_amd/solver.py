@@ -134,15 +134,19 @@ class Solver:
         A.check(st, self._h)
         self._keep = keep
 
-    def solve(self, b, x=None, tol=1e-6, allow_not_converged=False):
+    def solve(self, b, x=None, tol=1e-6, allow_not_converged=False, noalloc=False):
+        """noalloc=True calls cpr_solve_noalloc (no device allocation inside the
+        call; x must then be given, and the caller owns both vectors)."""
         torch = _torch()
         _check_device_vec(b, 3 * self.n_b, "b", self.device)
         if x is None:
+            if noalloc:
+                raise ValueError("noalloc solve needs a caller-allocated x")
             x = torch.zeros_like(b)
         _check_device_vec(x, 3 * self.n_b, "x", self.device)
         info = A.cpr_solve_info()
-        st = self._lib.cpr_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), float(tol),
-                                 C.byref(info))
+        fn = self._lib.cpr_solve_noalloc if noalloc else self._lib.cpr_solve
+        st = fn(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), float(tol), C.byref(info))
         allow = (A.CPR_OK, A.CPR_NOT_CONVERGED) if allow_not_converged else (A.CPR_OK,)
         A.check(st, self._h, allow)
         d = info.as_dict()
