@@ -21,7 +21,6 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-METRIC = "CPR-FGMRES time to relres 1e-6 @3.28M DOF, FP32 vs FP64 precond; p50/p99 lat"
 HBM_PEAK_GBS = 8000.0
 
 
@@ -262,6 +261,11 @@ def _measured_traffic(kernel, workload):
     return rec.get("hbm_bytes_per_launch")
 
 
+SECOND_STAGES = {"bgs": 0, "bilu": 1}
+DECOUPLINGS = {"none": 0, "quasi-impes": 1, "abf": 2}
+SMOOTHERS = {"pgs-scm": 0, "pgs-no": 1}
+
+
 def _params(args, **kw):
     from paper_2201_01970_amd import Params
 
@@ -269,7 +273,29 @@ def _params(args, **kw):
         kw["tail_nnz"] = args.tail_nnz
     if getattr(args, "row_layout", None) is not None:
         kw["row_layout"] = args.row_layout
+    kw.setdefault("second_stage", SECOND_STAGES[getattr(args, "second_stage", "bgs")])
+    kw.setdefault("decoupling", DECOUPLINGS[getattr(args, "decoupling", "none")])
+    kw.setdefault("smoother", SMOOTHERS[getattr(args, "smoother", "pgs-scm")])
+    if getattr(args, "chunks", None) is not None:
+        kw.setdefault("smoother_chunks", args.chunks)
+    if getattr(args, "theta_color", None) is not None:
+        kw.setdefault("theta_color", args.theta_color)
     return Params(**kw)
+
+
+def _metric(dof):
+    """The headline metric string, with the workload's size."""
+    size = "3.28M" if dof == 3281850 else f"{dof / 1e6:.3g}M"
+    return f"CPR-FGMRES time to relres 1e-6 @{size} DOF, FP32 vs FP64 precond; p50/p99 lat"
+
+
+def _method_config(args):
+    p = _params(args)
+    smoother = ("PGS-SCM theta=%g" % p.theta_color if p.smoother == 0
+                else "PGS-NO %d chunks" % p.smoother_chunks)
+    return {"amg": f"RS theta=0.25, coarse<=50, {smoother}, 2+2 sweeps",
+            "stage2": "multi-colour block GS" if p.second_stage == 0 else "block ILU(0), level-scheduled solves",
+            "decoupling": {0: "none", 1: "quasi-IMPES", 2: "ABF"}[p.decoupling]}
 
 
 def _case_for(args):
@@ -341,6 +367,110 @@ def newton_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def experiments_bench(args):
+    """The shapes of the paper's Section 6 experiments on the SPE10-sized grid
+    (FP32 preconditioner, FP64 FGMRES, tol 1e-6):
+      theta_launch: iterations and solve time for theta_c in {0, 0.05, 0.1,
+        0.3} under several storage forms / launch shapes of the level matrices
+        (the paper's thread counts): PGS-SCM's iterate does not change;
+      pgs_no: the natural-order chunked GS for several chunk counts: the
+        iterations drift with the chunk count;
+      mu: SetupCalls, iterations, SETUP share of the time for the paper's
+        absolute reuse rule (It > mu rebuilds) with mu in {0, 10, 20, 30, 40}
+        on 12-step Newton sequences with +-5% and +-20% drift per step."""
+    import hashlib
+
+    import numpy as np
+    import torch
+
+    from paper_2201_01970_amd import Params, Solver
+    from workloads import blackoil as bo
+
+    dev = torch.device("cuda:0")
+    shape = tuple(args.shape) if args.shape else (60, 220, 85)
+    case = bo.case_spe10_like(seed=1100, shape=shape)
+    b = torch.as_tensor(bo.rhs(case.ndof, 1101), device=dev)
+    rp = torch.as_tensor(case.row_ptr, device=dev)
+    col = torch.as_tensor(case.col, device=dev)
+    vals = torch.as_tensor(case.vals.reshape(-1), device=dev)
+    out = {"metric": "Section 6 experiment shapes: theta_c, launch shape, PGS-NO chunks, reuse threshold mu",
+           "config": {"workload": f"spe10-like {shape[0]}x{shape[1]}x{shape[2]}", "tol": args.tol,
+                      "precond": "FP32 preconditioner, FP64 FGMRES(30)"}, "data": "synthetic"}
+
+    def timed(p, reps=3):
+        S = Solver(rp, col, vals, p)
+        x = torch.zeros_like(b)
+        times, info = [], None
+        for _ in range(reps + 1):
+            x.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, info = S.solve(b, x, tol=args.tol)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t) * 1e3)
+        cols = [S.level_info(l)["n_colours"] for l in range(S.level_info(0)["n_levels"] - 1)]
+        S.close()
+        digest = hashlib.sha256(x.cpu().numpy().tobytes()).hexdigest()[:16]
+        return {"iterations": info["iterations"], "relres_true": info["relres_true"],
+                "median_ms": statistics.median(times[1:]), "x_sha256": digest, "colours": cols}
+
+    rows = []
+    for theta in (0.0, 0.05, 0.1, 0.3):
+        for shape_kw in (dict(row_layout=0), dict(row_layout=1), dict(row_layout=2), dict(row_layout=16),
+                         dict(tail_nnz=0)):
+            r = timed(Params(precond_fp32=True, theta_color=theta, **shape_kw))
+            r.update(theta_color=theta, **shape_kw)
+            rows.append(r)
+            print(f"[exp] theta {theta} {shape_kw}: its {r['iterations']} {r['median_ms']:.2f} ms "
+                  f"x {r['x_sha256']}", file=sys.stderr, flush=True)
+    out["theta_launch"] = rows
+    out["theta_launch_invariant"] = {
+        str(t): len({r["x_sha256"] for r in rows if r["theta_color"] == t}) == 1 for t in (0.0, 0.05, 0.1, 0.3)}
+
+    rows = []
+    for chunks in (1024, 4096, 16384, 65536, 262144):
+        r = timed(Params(precond_fp32=True, smoother=1, smoother_chunks=chunks), reps=1)
+        r.update(chunks=chunks)
+        rows.append(r)
+        print(f"[exp] pgs-no {chunks}: its {r['iterations']} {r['median_ms']:.2f} ms", file=sys.stderr, flush=True)
+    out["pgs_no"] = rows
+
+    res = {}
+    for amp in (0.05, 0.2):
+        steps = [(k, c.vals.reshape(-1).copy(), bb) for k, c, bb in
+                 bo.newton_sequence(n_steps=12, shape=shape, amp=amp)]
+        for mu in (0, 10, 20, 30, 40):
+            v0 = torch.as_tensor(steps[0][1], device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S = Solver(rp, col, v0, Params(precond_fp32=True, reuse_mode=1, mu=mu))
+            torch.cuda.synchronize()
+            first = time.perf_counter() - t0
+            total, setups, setup_ms, its = first, 1, first * 1e3, []
+            for k, v_np, b_np in steps:
+                bk = torch.as_tensor(b_np, device=dev)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                if k > 0:
+                    S.update_values(torch.as_tensor(v_np, device=dev))
+                _, info = S.solve(bk, tol=args.tol)
+                torch.cuda.synchronize()
+                total += time.perf_counter() - t
+                its.append(info["iterations"])
+                if info["rebuilt"]:
+                    setups += 1
+                    setup_ms += info["setup_ms"]
+            S.close()
+            key = f"amp{amp}_mu{mu}"
+            res[key] = {"amp": amp, "mu": mu, "setup_calls": setups, "iterations": its,
+                        "iterations_total": sum(its), "total_s": total,
+                        "setup_ratio": setup_ms / 1e3 / total if total else 0.0}
+            print(f"[exp] amp {amp} mu {mu}: setups {setups} its {sum(its)} {total:.2f} s", file=sys.stderr,
+                  flush=True)
+    out["mu"] = res
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -356,6 +486,8 @@ def main():
     ap.add_argument("--newton", action="store_true", help="run the Newton-sequence benchmark instead")
     ap.add_argument("--newton-steps", type=int, default=12)
     ap.add_argument("--serve", action="store_true", help="run the serving-stream benchmark instead")
+    ap.add_argument("--experiments", action="store_true",
+                    help="run the theta / launch-shape / PGS-NO / mu experiment tables instead")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--saturation-requests", type=int, default=64)
     ap.add_argument("--rate", type=float, default=0.0, help="arrival rate per second (default 0.8 x saturation)")
@@ -364,6 +496,12 @@ def main():
     ap.add_argument("--gen-procs", type=int, default=12)
     ap.add_argument("--tail-nnz", type=int, default=None, help="override Params.tail_nnz")
     ap.add_argument("--row-layout", type=int, default=None, help="override Params.row_layout")
+    ap.add_argument("--second-stage", choices=sorted(SECOND_STAGES), default="bgs",
+                    help="R of the CPR preconditioner: multi-colour block GS or block ILU(0)")
+    ap.add_argument("--decoupling", choices=sorted(DECOUPLINGS), default="none")
+    ap.add_argument("--smoother", choices=sorted(SMOOTHERS), default="pgs-scm")
+    ap.add_argument("--chunks", type=int, default=None, help="PGS-NO chunks per level")
+    ap.add_argument("--theta-color", type=float, default=None, help="colouring threshold of PGS-SCM")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solve of one Jacobian is not "
@@ -374,6 +512,9 @@ def main():
         return
     if args.newton:
         newton_bench(args)
+        return
+    if args.experiments:
+        experiments_bench(args)
         return
 
     import numpy as np
@@ -479,7 +620,7 @@ def main():
 
     med32 = statistics.median(r32["times"])
     out = {
-        "metric": METRIC,
+        "metric": _metric(case.ndof),
         "value": med32,
         "unit": "ms",
         "n_gpus": 1,
@@ -492,9 +633,7 @@ def main():
         "dtype": "f32 preconditioner / f64 FGMRES",
         "data": "synthetic",
         "config": {"workload": workload, "n_cells": case.n_b, "dof": case.ndof, "nnz_blocks": case.nnz_b,
-                   "tol": args.tol, "krylov": "FGMRES(30)",
-                   "amg": "RS theta=0.25, coarse<=50, PGS-SCM theta=0.05, 2+2 sweeps",
-                   "stage2": "multi-colour block GS",
+                   "tol": args.tol, "krylov": "FGMRES(30)", **_method_config(args),
                    "tail_nnz": _params(args).tail_nnz, "row_layout": _params(args).row_layout},
         "p50_ms": _pct(r32["times"], 0.5),
         "p99_ms": _pct(r32["times"], 0.99),

@@ -92,6 +92,24 @@ typedef struct {
                              multiple of four entries) everywhere; 16/32/64 = CSR read by
                              lane groups of that size everywhere.  Levels run by the
                              single-workgroup kernel always use quad-vector CSR [0] */
+  int32_t second_stage;   /* R of eq. (CPR): 0 = one forward multi-colour block
+                             Gauss-Seidel sweep; 1 = block ILU(0) in natural order,
+                             applied with level-scheduled triangular solves (the
+                             paper's R, Sections 3.1 and 6) [0] */
+  int32_t decoupling;     /* rows multiplied by a block-diagonal W before B is built
+                             (B is built on W A and applied to W v; the outer FGMRES
+                             keeps A): 0 = none; 1 = quasi-IMPES (W_i = I with
+                             (0,1) = -D_01/D_11, (0,2) = -D_02/D_22 of the diagonal
+                             block D_i); 2 = alternate block factorisation (W_i =
+                             D_i^-1) [0] */
+  int32_t smoother;       /* AMG smoother: 0 = PGS-SCM (Algorithm "PGS-SCM", colours of
+                             eq. (strong-matrix)); 1 = PGS-NO, the natural-order
+                             parallel Gauss-Seidel PGS-SCM is compared with in
+                             Section 6: rows split into smoother_chunks contiguous
+                             chunks, Gauss-Seidel inside a chunk, values of other chunks
+                             as they were when the sweep started [0] */
+  int32_t smoother_chunks;/* chunks of the PGS-NO smoother on every level (rows per
+                             chunk = ceil(n / chunks)) [256] */
 } cpr_params;
 
 typedef struct {

@@ -43,6 +43,13 @@ cpr_status cpr_vcycle(cpr_handle* h, const double* r, double* e);
 cpr_status cpr_smooth(cpr_handle* h, int32_t level, double* x, const double* b, int32_t n_sweeps,
                       int32_t zero_start);
 
+/* z = Pi_P pe + R (v - A Pi_P pe): the second stage of Algorithm "CPR
+ * method" given a stage-1 pressure correction pe, with the handle's R (block
+ * Gauss-Seidel or block ILU(0), cpr_params.second_stage) and the copy of A
+ * the preconditioner was built on, in the preconditioner's precision.
+ * v, z: 3*n_block_rows doubles; pe: n_block_rows doubles (cell order). */
+cpr_status cpr_second_stage(cpr_handle* h, const double* v, const double* pe, double* z);
+
 /* ---- products of SETUP (host arrays, filled from the handle) ---------- */
 
 /* out[0..7] = n_rows, nnz, n_colours, n_coarse (rows of level+1, 0 on the
@@ -66,6 +73,15 @@ cpr_status cpr_level_interp(const cpr_handle* h, int32_t level, int32_t* row_ptr
 
 /* Colour of every cell in the stage-2 block colouring (int32[n_block_rows]). */
 cpr_status cpr_block_colours(const cpr_handle* h, int32_t* colour);
+
+/* The block ILU(0) factors of a handle whose second stage is block ILU(0)
+ * (Sections 3.1 and 6), FP64, in the input block order: lu[nnz_blocks*9]
+ * holds L_ik (k < i) and U_ij (j >= i, U_ii before inversion), uinv[n*9] the
+ * inverted pivot blocks, flev/blev[n] the level of every row in the forward
+ * and backward solve; n_levels[2] receives the two level counts.  Any array
+ * may be NULL.  CPR_ERR_INVALID_ARG when the second stage is block GS. */
+cpr_status cpr_bilu_factors(const cpr_handle* h, double* lu, double* uinv, int32_t* flev, int32_t* blev,
+                            int32_t* n_levels);
 
 /* ---- host-only SETUP routines (no GPU work; for CPU tests) ------------- */
 
@@ -95,6 +111,15 @@ cpr_status cpr_host_interpolation(int32_t n, const int32_t* a_ptr, const int32_t
 cpr_status cpr_host_galerkin(int32_t n, int32_t n_coarse, const int32_t* a_ptr, const int32_t* a_col,
                              const double* a_val, const int32_t* p_ptr, const int32_t* p_col,
                              const double* p_val, int32_t* c_ptr, int32_t* c_col, double* c_val);
+
+/* Block ILU(0) (the second stage R of eq. (CPR) named in Section 3.1, with
+ * the level scheduling of Section 6) of a 3x3-block matrix with sorted
+ * columns and stored diagonal blocks: vals[nnz*9] in, lu[nnz*9] (L_ik for
+ * k < i, U_ij for j >= i), uinv[n*9] (inverted pivot blocks), flev/blev[n]
+ * (forward / backward level of every row) out.  CPR_ERR_SINGULAR_BLOCK when
+ * a pivot block is singular. */
+cpr_status cpr_host_bilu0(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* vals, double* lu,
+                          double* uinv, int32_t* flev, int32_t* blev);
 
 /* ---- measurement ------------------------------------------------------ */
 

@@ -65,6 +65,10 @@ class cpr_params(C.Structure):
         ("use_graphs", C.c_int32),
         ("tail_nnz", C.c_int32),
         ("row_layout", C.c_int32),
+        ("second_stage", C.c_int32),
+        ("decoupling", C.c_int32),
+        ("smoother", C.c_int32),
+        ("smoother_chunks", C.c_int32),
     ]
 
 
@@ -114,6 +118,8 @@ SIGNATURES = {
     "cpr_setup": (_I32, [C.POINTER(cpr_bsr), C.POINTER(cpr_params), _P, C.POINTER(_P)]),
     "cpr_update_values": (_I32, [_P, C.POINTER(cpr_bsr)]),
     "cpr_solve": (_I32, [_P, _P, _P, _D, C.POINTER(cpr_solve_info)]),
+    "cpr_second_stage": (_I32, [_P, _P, _P, _P]),
+    "cpr_bilu_factors": (_I32, [_P, _P, _P, _P, _P, _P]),
     "cpr_solve_noalloc": (_I32, [_P, _P, _P, _D, C.POINTER(cpr_solve_info)]),
     "cpr_set_stream": (_I32, [_P, _P]),
     "cpr_destroy": (None, [_P]),
@@ -131,6 +137,7 @@ SIGNATURES = {
     "cpr_host_grouping": (_I32, [_I32, _P, _P, _P, _P]),
     "cpr_host_rs_split": (_I32, [_I32, _P, _P, _P]),
     "cpr_host_interpolation": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "cpr_host_bilu0": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _P]),
     "cpr_host_galerkin": (_I32, [_I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "cpr_profile_enable": (_I32, [_P, _I32]),
     "cpr_profile_read": (_I32, [_P, _I32, _P, _P, _P]),

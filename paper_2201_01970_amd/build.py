@@ -27,6 +27,8 @@ SOURCES = [
     "kernels_krylov.hip",
     "kernels_tail.hip",
     "noalloc.hip",
+    "kernels_bilu.hip",
+    "kernels_decouple.hip",
 ]
 
 ARCH = os.environ.get("CPR_OFFLOAD_ARCH", "gfx950")

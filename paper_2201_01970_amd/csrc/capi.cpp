@@ -153,6 +153,10 @@ void cpr_params_default(cpr_params* p) {
   p->use_graphs = 1;
   p->tail_nnz = 30000;
   p->row_layout = 0;
+  p->second_stage = 0;
+  p->decoupling = 0;
+  p->smoother = 0;
+  p->smoother_chunks = 256;
 }
 
 cpr_status cpr_setup(const cpr_bsr* A, const cpr_params* p, void* hip_stream, cpr_handle** out) {
@@ -168,7 +172,9 @@ cpr_status cpr_setup(const cpr_bsr* A, const cpr_params* p, void* hip_stream, cp
         prm.pre_sweeps < 0 || prm.post_sweeps < 0 || !(prm.theta_rs >= 0.0) || !(prm.theta_color >= 0.0) ||
         prm.reuse_mode < 0 || prm.reuse_mode > 2 || prm.tail_nnz < 0 ||
         !(prm.row_layout == 0 || prm.row_layout == 1 || prm.row_layout == 2 || prm.row_layout == 4 ||
-          prm.row_layout == 16 || prm.row_layout == 32 || prm.row_layout == 64))
+          prm.row_layout == 16 || prm.row_layout == 32 || prm.row_layout == 64) ||
+        prm.second_stage < 0 || prm.second_stage > 1 || prm.decoupling < 0 || prm.decoupling > 2 ||
+        prm.smoother < 0 || prm.smoother > 1 || prm.smoother_chunks < 1)
       throw Error(CPR_ERR_INVALID_ARG, "invalid parameters");
     h = new cpr_handle();
     h->prm = prm;
@@ -349,6 +355,16 @@ cpr_status cpr_precond_apply(cpr_handle* h, const double* v, double* z) {
   });
 }
 
+cpr_status cpr_second_stage(cpr_handle* h, const double* v, const double* pe, double* z) {
+  if (!h || !v || !pe || !z) return fail(h, CPR_ERR_INVALID_ARG, "null argument");
+  return guarded(h, [&]() -> cpr_status {
+    need_pc(h);
+    h->pc->second_stage_own(v, pe, z, h->stream);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return CPR_OK;
+  });
+}
+
 cpr_status cpr_vcycle(cpr_handle* h, const double* r, double* e) {
   if (!h || !r || !e) return fail(h, CPR_ERR_INVALID_ARG, "null argument");
   return guarded(h, [&]() -> cpr_status {
@@ -416,6 +432,22 @@ cpr_status cpr_level_interp(const cpr_handle* h, int32_t level, int32_t* row_ptr
 cpr_status cpr_block_colours(const cpr_handle* h, int32_t* colour) {
   if (!h || !colour) return fail(const_cast<cpr_handle*>(h), CPR_ERR_INVALID_ARG, "null argument");
   std::copy(h->block_colour.begin(), h->block_colour.end(), colour);
+  return CPR_OK;
+}
+
+cpr_status cpr_bilu_factors(const cpr_handle* h, double* lu, double* uinv, int32_t* flev, int32_t* blev,
+                            int32_t* n_levels) {
+  if (!h) return fail(nullptr, CPR_ERR_INVALID_ARG, "null handle");
+  const HostBilu& F = h->bilu_host;
+  if (F.flev.empty()) return fail(const_cast<cpr_handle*>(h), CPR_ERR_INVALID_ARG, "the second stage is not block ILU(0)");
+  if (lu) std::copy(F.lu.begin(), F.lu.end(), lu);
+  if (uinv) std::copy(F.uinv.begin(), F.uinv.end(), uinv);
+  if (flev) std::copy(F.flev.begin(), F.flev.end(), flev);
+  if (blev) std::copy(F.blev.begin(), F.blev.end(), blev);
+  if (n_levels) {
+    n_levels[0] = F.n_flev;
+    n_levels[1] = F.n_blev;
+  }
   return CPR_OK;
 }
 
@@ -495,6 +527,23 @@ cpr_status cpr_host_galerkin(int32_t n, int32_t n_coarse, const int32_t* a_ptr, 
     std::copy(C.ptr.begin(), C.ptr.end(), c_ptr);
     if (c_col) std::copy(C.col.begin(), C.col.end(), c_col);
     if (c_val) std::copy(C.val.begin(), C.val.end(), c_val);
+    return CPR_OK;
+  });
+}
+
+cpr_status cpr_host_bilu0(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* vals, double* lu,
+                          double* uinv, int32_t* flev, int32_t* blev) {
+  if (n < 0 || !row_ptr || !col || !vals || !lu || !uinv || !flev || !blev)
+    return fail(nullptr, CPR_ERR_INVALID_ARG, "invalid argument");
+  return guarded(nullptr, [&]() -> cpr_status {
+    std::vector<int32_t> fl, bl;
+    bilu_forward_levels(n, row_ptr, col, fl);
+    bilu_backward_levels(n, row_ptr, col, bl);
+    std::copy(vals, vals + static_cast<int64_t>(row_ptr[n]) * 9, lu);
+    const int32_t bad = bilu0_factor(n, row_ptr, col, fl, lu, uinv);
+    std::copy(fl.begin(), fl.end(), flev);
+    std::copy(bl.begin(), bl.end(), blev);
+    if (bad >= 0) throw Error(CPR_ERR_SINGULAR_BLOCK, "pivot block of row " + std::to_string(bad) + " is singular");
     return CPR_OK;
   });
 }

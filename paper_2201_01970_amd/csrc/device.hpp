@@ -92,6 +92,38 @@ template <typename T>
 void launch_stage2(const SellView<T>& A, int32_t lo, int32_t hi, const int32_t* cell, const T* dinv,
                    int32_t dinv_ld, const double* v, const T* pe, T* z, hipStream_t s);
 
+// Block ILU(0) second stage.  Residual (all rows, natural order; R = column 0
+// of every stored block, 3 planes): r_i = v_i - sum_j A_ij (pe_j, 0, 0).
+// One level of each triangular solve (positions [lo, hi) of that solve's
+// level order, row[q] = cell): forward, L = the lower factor blocks (9
+// planes), y_i = r_i - sum_{k<i} L_ik y_k; backward, U = the upper blocks,
+// uinv[e*ld + q] the inverted pivot blocks, d_i = Uinv_i (y_i - sum_{j>i}
+// U_ij d_j), z_i = (pe_i + d_i0, d_i1, d_i2).
+template <typename T>
+void launch_bilu_residual(const SellView<T>& R, const double* v, const T* pe, T* r, hipStream_t s);
+template <typename T>
+void launch_bilu_forward(int32_t lo, int32_t hi, const SellView<T>& L, const int32_t* row, const T* r, T* y,
+                         hipStream_t s);
+template <typename T>
+void launch_bilu_backward(int32_t lo, int32_t hi, const SellView<T>& U, const T* uinv, int32_t ld, const int32_t* row,
+                          const T* y, const T* pe, T* d, T* z, hipStream_t s);
+
+// One PGS-NO sweep (in place on x) of a CSR level matrix in natural row order
+// (A.group 2 or 4: rows padded with column -1): n_chunks contiguous chunks,
+// Gauss-Seidel inside a chunk, other chunks' values from snap (null: 0).
+template <typename T>
+void launch_gs_chunks(const MatView<T>& A, const T* diag, int32_t n_chunks, const T* b, T* x, const T* snap,
+                      hipStream_t s);
+
+// Decoupling (kind 1 quasi-IMPES, 2 ABF): w[9i..] = W_i from the diagonal
+// block of row i, wa[9k..] = W_i A_k for every stored block k of row i (FP64,
+// input order); *bad_row = min(*bad_row, i) for rows whose W_i cannot be formed.
+void launch_decouple(int32_t n, const int32_t* rp, const int32_t* col, const double* vals, int32_t kind, double* w,
+                     double* wa, int32_t* bad_row, hipStream_t s);
+// out[3i+r] = (W_i v_i)_r computed in T from (T)v, stored as FP64; w: n x 9 in T.
+template <typename T>
+void launch_block_gemv(int32_t n, const T* w, const double* v, double* out, hipStream_t s);
+
 // Inverse of the diagonal blocks (LU with partial pivoting), planes dinv[e*ld + q];
 // diag_pos[q] = index of the diagonal block of cell cell[q] in the input BSR.
 // singular[0] is set to 1 when a pivot is below 1e-300 * max|block|.

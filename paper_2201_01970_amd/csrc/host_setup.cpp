@@ -2,6 +2,7 @@
 #include "host_setup.hpp"
 
 #include <algorithm>
+#include <limits>
 #include <atomic>
 #include <cmath>
 #include <condition_variable>
@@ -632,6 +633,153 @@ bool dense_lu(int32_t n, std::vector<double>& a, std::vector<int32_t>& piv) {
     }
   }
   return true;
+}
+
+// ------------------------------------------------------------ block ILU(0)
+bool inverse3(const double* src, double* out) {
+  double a[3][3];
+  double amax = 0.0;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      a[r][c] = src[3 * r + c];
+      amax = std::max(amax, std::fabs(a[r][c]));
+    }
+  int perm[3] = {0, 1, 2};
+  bool ok = amax > 0.0;
+  for (int k = 0; k < 3; ++k) {
+    int p = k;
+    double best = std::fabs(a[k][k]);
+    for (int r = k + 1; r < 3; ++r)
+      if (std::fabs(a[r][k]) > best) {
+        best = std::fabs(a[r][k]);
+        p = r;
+      }
+    if (!(best > 1e-300 * amax)) ok = false;
+    if (p != k) {
+      for (int c = 0; c < 3; ++c) std::swap(a[k][c], a[p][c]);
+      std::swap(perm[k], perm[p]);
+    }
+    for (int r = k + 1; r < 3; ++r) {
+      a[r][k] = a[r][k] / a[k][k];
+      for (int c = k + 1; c < 3; ++c) a[r][c] = a[r][c] - a[r][k] * a[k][c];
+    }
+  }
+  if (!ok) return false;
+  // column c of the inverse solves (L U) x = P e_c
+  for (int c = 0; c < 3; ++c) {
+    double y[3];
+    for (int r = 0; r < 3; ++r) {
+      double t = perm[r] == c ? 1.0 : 0.0;
+      for (int m = 0; m < r; ++m) t = t - a[r][m] * y[m];
+      y[r] = t;
+    }
+    for (int r = 2; r >= 0; --r) {
+      double t = y[r];
+      for (int m = r + 1; m < 3; ++m) t = t - a[r][m] * y[m];
+      y[r] = t / a[r][r];
+    }
+    for (int r = 0; r < 3; ++r) out[3 * r + c] = y[r];
+  }
+  return true;
+}
+
+namespace {
+
+// c = a b for row-major 3x3 blocks, each entry summed from 0.0 over m.
+inline void mul3(const double* a, const double* b, double* c) {
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 3; ++q) {
+      double t = 0.0;
+      for (int m = 0; m < 3; ++m) t = t + a[3 * r + m] * b[3 * m + q];
+      c[3 * r + q] = t;
+    }
+}
+
+}  // namespace
+
+int32_t bilu_forward_levels(int32_t n, const int32_t* rp, const int32_t* col, std::vector<int32_t>& lev) {
+  lev.assign(n, 0);
+  int32_t nlev = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t m = -1;
+    for (int32_t p = rp[i]; p < rp[i + 1] && col[p] < i; ++p) m = std::max(m, lev[col[p]]);
+    lev[i] = m + 1;
+    nlev = std::max(nlev, m + 2);
+  }
+  return nlev;
+}
+
+int32_t bilu_backward_levels(int32_t n, const int32_t* rp, const int32_t* col, std::vector<int32_t>& lev) {
+  lev.assign(n, 0);
+  int32_t nlev = 0;
+  for (int32_t i = n - 1; i >= 0; --i) {
+    int32_t m = -1;
+    for (int32_t p = rp[i + 1] - 1; p >= rp[i] && col[p] > i; --p) m = std::max(m, lev[col[p]]);
+    lev[i] = m + 1;
+    nlev = std::max(nlev, m + 2);
+  }
+  return nlev;
+}
+
+int32_t bilu0_factor(int32_t n, const int32_t* rp, const int32_t* col, const std::vector<int32_t>& flev,
+                     double* lu, double* uinv) {
+  // rows grouped by forward level (ascending index inside a level)
+  int32_t nlev = 0;
+  for (int32_t i = 0; i < n; ++i) nlev = std::max(nlev, flev[i] + 1);
+  std::vector<int32_t> off(nlev + 1, 0), rows(n);
+  for (int32_t i = 0; i < n; ++i) off[flev[i] + 1]++;
+  for (int32_t l = 0; l < nlev; ++l) off[l + 1] += off[l];
+  {
+    std::vector<int32_t> next(off.begin(), off.end() - 1);
+    for (int32_t i = 0; i < n; ++i) rows[next[flev[i]]++] = i;
+  }
+  std::atomic<int32_t> bad{std::numeric_limits<int32_t>::max()};
+  auto factor_row = [&](int32_t i) {
+    const int32_t a = rp[i], b = rp[i + 1];
+    int32_t dpos = -1;
+    for (int32_t p = a; p < b; ++p) {
+      const int32_t k = col[p];
+      if (k == i) dpos = p;
+      if (k >= i) continue;
+      double l[9];
+      mul3(lu + 9 * static_cast<int64_t>(p), uinv + 9 * static_cast<int64_t>(k), l);
+      std::copy(l, l + 9, lu + 9 * static_cast<int64_t>(p));
+      // A_ij -= L_ik U_kj over the j > k that both rows store (both sorted)
+      int32_t t = p + 1;
+      for (int32_t q = rp[k]; q < rp[k + 1]; ++q) {
+        const int32_t j = col[q];
+        if (j <= k) continue;
+        while (t < b && col[t] < j) ++t;
+        if (t == b) break;
+        if (col[t] != j) continue;
+        double prod[9];
+        mul3(l, lu + 9 * static_cast<int64_t>(q), prod);
+        double* dst = lu + 9 * static_cast<int64_t>(t);
+        for (int e = 0; e < 9; ++e) dst[e] = dst[e] - prod[e];
+      }
+    }
+    if (dpos < 0 || !inverse3(lu + 9 * static_cast<int64_t>(dpos), uinv + 9 * static_cast<int64_t>(i))) {
+      int32_t cur = bad.load();
+      while (i < cur && !bad.compare_exchange_weak(cur, i)) {
+      }
+    }
+  };
+  for (int32_t l = 0; l < nlev; ++l) {
+    const int32_t r0 = off[l], r1 = off[l + 1], cnt = r1 - r0;
+    if (cnt < 4096) {
+      for (int32_t q = r0; q < r1; ++q) factor_row(rows[q]);
+    } else {
+      const int nch = std::min(64, cnt / 1024);
+      parallel_for(nch, [&](int ch, int) {
+        const int32_t q0 = r0 + static_cast<int32_t>(static_cast<int64_t>(cnt) * ch / nch);
+        const int32_t q1 = r0 + static_cast<int32_t>(static_cast<int64_t>(cnt) * (ch + 1) / nch);
+        for (int32_t q = q0; q < q1; ++q) factor_row(rows[q]);
+      });
+    }
+    if (bad.load() != std::numeric_limits<int32_t>::max()) break;
+  }
+  const int32_t first_bad = bad.load();
+  return first_bad == std::numeric_limits<int32_t>::max() ? -1 : first_bad;
 }
 
 }  // namespace cpr

@@ -100,6 +100,35 @@ HostCsr spgemm_ordered(const HostCsr& A, const HostCsr& B);
 // indices in piv.  Returns false when a pivot is exactly zero.
 bool dense_lu(int32_t n, std::vector<double>& a, std::vector<int32_t>& piv);
 
+// Block ILU(0) of a 3x3-block matrix (the second stage R of eq. (CPR) that
+// Section 3.1 names, with the level scheduling of Section 6), natural row
+// order, no fill: the factors keep A's block pattern.  IKJ form: for each row
+// i ascending, for each stored k < i ascending, L_ik = A_ik Uinv_k, then
+// A_ij -= L_ik U_kj for every stored j > k of row k that row i also stores;
+// then Uinv_i = inverse of the updated diagonal block (LU with partial
+// pivoting of the 3x3 block, then its inverse column by column).  A 3x3
+// product c = a b sums each entry from 0.0 over m = 0, 1, 2.  Rows of one
+// forward level depend only on rows of earlier levels, so the levels are
+// factored one after another, their rows in parallel.
+//   rp, col: the block pattern (sorted columns, diagonal stored);
+//   lu: on entry the blocks of A (nnz x 9, row-major), on exit L_ik (k < i)
+//       and U_ij (j >= i);  uinv: n x 9;  flev: forward level of every row.
+// Returns the first row whose pivot block is singular (a pivot below 1e-300
+// times the block's largest entry), or -1.
+int32_t bilu0_factor(int32_t n, const int32_t* rp, const int32_t* col, const std::vector<int32_t>& flev,
+                     double* lu, double* uinv);
+
+// Level of every row in the forward (lower) and backward (upper) triangular
+// solve: 0 when the row has no stored entry on that side, else one more than
+// the largest level among those entries.  Returns the number of levels.
+int32_t bilu_forward_levels(int32_t n, const int32_t* rp, const int32_t* col, std::vector<int32_t>& lev);
+int32_t bilu_backward_levels(int32_t n, const int32_t* rp, const int32_t* col, std::vector<int32_t>& lev);
+
+// Inverse of a 3x3 block (row-major) by LU with partial pivoting, then the
+// inverse column by column; false when a pivot is at most 1e-300 times the
+// block's largest entry.
+bool inverse3(const double* a, double* inv);
+
 // Host threads used by the row-parallel SETUP steps (at most 16).
 int setup_threads();
 

@@ -309,6 +309,51 @@ template void launch_gs_colour<double>(const MatView<double>&, const double*, in
 template void launch_gs_colour<float>(const MatView<float>&, const float*, int32_t, int32_t, const float*, float*,
                                       const float*, float*, bool, hipStream_t);
 
+// ------------------------------------------------------------------ PGS-NO
+// The natural-order parallel Gauss-Seidel that Section 6 compares PGS-SCM
+// with: the rows (natural order, CSR with rows padded by column -1) are split
+// into nch contiguous chunks, the first r of q+1 rows and the rest of q rows;
+// one lane walks its chunk in row order, reading the newest values of its own
+// chunk's rows and, for rows of other chunks, the values of the sweep's start
+// (snap, or 0 when snap is null: the sweep starts from x = 0).  Per row:
+// s = b_i, s = s - a_ij * xt_j over stored j != i in stored order, x_i = s / a_ii.
+template <typename T>
+__global__ __launch_bounds__(64) void k_gs_chunks(int32_t nch, int32_t q, int32_t r, const int32_t* __restrict__ ptr,
+                                                  const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                  const T* __restrict__ diag, const T* __restrict__ b, T* x,
+                                                  const T* __restrict__ snap) {
+  const int32_t c = blockIdx.x * 64 + threadIdx.x;
+  if (c >= nch) return;
+  const int32_t lo = c * q + (c < r ? c : r);
+  const int32_t hi = lo + q + (c < r ? 1 : 0);
+  for (int32_t i = lo; i < hi; ++i) {
+    T s = b[i];
+    for (int32_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+      const int32_t j = col[e];
+      if (j < 0 || j == i) continue;
+      const T xt = (j >= lo && j < hi) ? x[j] : (snap ? snap[j] : (T)0);
+      s = s - val[e] * xt;
+    }
+    x[i] = s / diag[i];
+  }
+}
+
+template <typename T>
+void launch_gs_chunks(const MatView<T>& A, const T* diag, int32_t n_chunks, const T* b, T* x, const T* snap,
+                      hipStream_t s) {
+  const int32_t n = A.n_rows;
+  if (n == 0) return;
+  const int32_t nch = n_chunks < 1 ? 1 : (n_chunks > n ? n : n_chunks);
+  const int32_t q = n / nch, r = n % nch;
+  hipLaunchKernelGGL((k_gs_chunks<T>), dim3(div_up(nch, 64)), dim3(64), 0, s, nch, q, r, A.ptr, A.col, A.val, diag, b,
+                     x, snap);
+  CPR_LAUNCH_CHECK();
+}
+template void launch_gs_chunks<double>(const MatView<double>&, const double*, int32_t, const double*, double*,
+                                       const double*, hipStream_t);
+template void launch_gs_chunks<float>(const MatView<float>&, const float*, int32_t, const float*, float*, const float*,
+                                      hipStream_t);
+
 // ------------------------------------------------------------------ row products
 // MODE 0: y = b - A x (residual; products subtracted from b in stored order)
 // MODE 1: y = A x (sum from 0 in stored order)

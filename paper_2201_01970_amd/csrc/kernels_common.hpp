@@ -259,6 +259,62 @@ __device__ __forceinline__ T row16v4_sub(T s, int32_t p0, int32_t p1, ColP col, 
   return s;
 }
 
+// Inverse of a 3x3 block (row-major src, FP64) by LU with partial pivoting,
+// then column c of the inverse from (L U) x = P e_c.  Returns false when a
+// pivot is not above 1e-300 times the block's largest entry (or the block is
+// zero); out is then unspecified.
+__device__ inline bool inverse3x3(const double* src, double out[9]) {
+  double a[3][3];
+  double amax = 0.0;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      a[r][c] = src[3 * r + c];
+      amax = fmax(amax, fabs(a[r][c]));
+    }
+  int perm[3] = {0, 1, 2};
+  bool bad = !(amax > 0.0);
+  for (int k = 0; k < 3; ++k) {
+    int p = k;
+    double best = fabs(a[k][k]);
+    for (int r = k + 1; r < 3; ++r)
+      if (fabs(a[r][k]) > best) {
+        best = fabs(a[r][k]);
+        p = r;
+      }
+    if (!(best > 1e-300 * amax)) bad = true;
+    if (p != k) {
+      for (int c = 0; c < 3; ++c) {
+        const double tmp = a[k][c];
+        a[k][c] = a[p][c];
+        a[p][c] = tmp;
+      }
+      const int tp = perm[k];
+      perm[k] = perm[p];
+      perm[p] = tp;
+    }
+    for (int r = k + 1; r < 3; ++r) {
+      a[r][k] = a[r][k] / a[k][k];
+      for (int c = k + 1; c < 3; ++c) a[r][c] = a[r][c] - a[r][k] * a[k][c];
+    }
+  }
+  if (bad) return false;
+  for (int c = 0; c < 3; ++c) {
+    double y[3];
+    for (int r = 0; r < 3; ++r) {
+      double s = (perm[r] == c) ? 1.0 : 0.0;
+      for (int k = 0; k < r; ++k) s = s - a[r][k] * y[k];
+      y[r] = s;
+    }
+    for (int r = 2; r >= 0; --r) {
+      double s = y[r];
+      for (int k = r + 1; k < 3; ++k) s = s - a[r][k] * y[k];
+      y[r] = s / a[r][r];
+    }
+    for (int r = 0; r < 3; ++r) out[3 * r + c] = y[r];
+  }
+  return true;
+}
+
 #define CPR_LAUNCH_CHECK() (void)hipGetLastError()
 
 }  // namespace cpr

@@ -220,59 +220,13 @@ __global__ __launch_bounds__(kBlock) void k_block_inverse(int32_t n, const doubl
                                                           int32_t* __restrict__ singular) {
   const int32_t q = blockIdx.x * kBlock + threadIdx.x;
   if (q >= n) return;
-  double a[3][3];
-  const double* src = vals + 9 * diag_pos[q];
-  double amax = 0.0;
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) {
-      a[r][c] = src[3 * r + c];
-      amax = fmax(amax, fabs(a[r][c]));
-    }
-  int perm[3] = {0, 1, 2};
-  bool bad = !(amax > 0.0);
-  for (int k = 0; k < 3; ++k) {
-    int p = k;
-    double best = fabs(a[k][k]);
-    for (int r = k + 1; r < 3; ++r)
-      if (fabs(a[r][k]) > best) {
-        best = fabs(a[r][k]);
-        p = r;
-      }
-    if (!(best > 1e-300 * amax)) bad = true;
-    if (p != k) {
-      for (int c = 0; c < 3; ++c) {
-        const double tmp = a[k][c];
-        a[k][c] = a[p][c];
-        a[p][c] = tmp;
-      }
-      const int tp = perm[k];
-      perm[k] = perm[p];
-      perm[p] = tp;
-    }
-    for (int r = k + 1; r < 3; ++r) {
-      a[r][k] = a[r][k] / a[k][k];
-      for (int c = k + 1; c < 3; ++c) a[r][c] = a[r][c] - a[r][k] * a[k][c];
-    }
-  }
-  if (bad) {
+  double inv[9];
+  if (!inverse3x3(vals + 9 * diag_pos[q], inv)) {
     singular[0] = 1;
     for (int e = 0; e < 9; ++e) dinv[(int64_t)e * ld + q] = (T)0;
     return;
   }
-  for (int c = 0; c < 3; ++c) {
-    double y[3];
-    for (int r = 0; r < 3; ++r) {
-      double s = (perm[r] == c) ? 1.0 : 0.0;
-      for (int k = 0; k < r; ++k) s = s - a[r][k] * y[k];
-      y[r] = s;
-    }
-    for (int r = 2; r >= 0; --r) {
-      double s = y[r];
-      for (int k = r + 1; k < 3; ++k) s = s - a[r][k] * y[k];
-      y[r] = s / a[r][r];
-    }
-    for (int r = 0; r < 3; ++r) dinv[(int64_t)(3 * r + c) * ld + q] = (T)y[r];
-  }
+  for (int e = 0; e < 9; ++e) dinv[(int64_t)e * ld + q] = (T)inv[e];
 }
 
 // SETUP's view of the input values, one thread per block row i (rows and

@@ -294,6 +294,82 @@ std::vector<int32_t> inverse_perm(const std::vector<int32_t>& perm) {
   return inv;
 }
 
+// Rows grouped by level (ascending index inside a level): order[q] = row,
+// off[l] = first position of level l.
+void level_order(const std::vector<int32_t>& lev, int32_t nlev, std::vector<int32_t>& order,
+                 std::vector<int32_t>& off) {
+  const int32_t n = static_cast<int32_t>(lev.size());
+  off.assign(nlev + 1, 0);
+  for (int32_t i = 0; i < n; ++i) off[lev[i] + 1]++;
+  for (int32_t l = 0; l < nlev; ++l) off[l + 1] += off[l];
+  std::vector<int32_t> next(off.begin(), off.end() - 1);
+  order.resize(n);
+  for (int32_t i = 0; i < n; ++i) order[next[lev[i]]++] = i;
+}
+
+// Block SELL-64 image of the rows order[q]: for row i, the stored blocks k of
+// [rp[i], rp[i+1]) whose column passes keep(i, col[k]), in stored order; a
+// block contributes `planes` values src[k*stride + e] (e < planes), one plane
+// each; rows are padded at the end with column -1 and zero values.
+template <typename T>
+struct BlockSellHost {
+  std::vector<int32_t> sp;
+  HostVec<int32_t> col;
+  HostVec<T> val;
+};
+
+template <typename T, typename Keep>
+BlockSellHost<T> build_block_sell(const std::vector<int32_t>& order, const HostVec<int32_t>& rp,
+                                  const HostVec<int32_t>& col, const double* src, int stride, int planes, Keep keep) {
+  BlockSellHost<T> S;
+  const int32_t n = static_cast<int32_t>(order.size());
+  const int32_t ns = (n + kWave - 1) / kWave;
+  S.sp.assign(ns + 1, 0);
+  for (int32_t s = 0; s < ns; ++s) {
+    int32_t w = 0;
+    for (int32_t q = s * kWave; q < std::min(n, (s + 1) * kWave); ++q) {
+      const int32_t i = order[q];
+      int32_t c = 0;
+      for (int32_t k = rp[i]; k < rp[i + 1]; ++k) c += keep(i, col[k]) ? 1 : 0;
+      w = std::max(w, c);
+    }
+    S.sp[s + 1] = S.sp[s] + w;
+  }
+  const int64_t slots = S.sp[ns];
+  S.col.resize(static_cast<size_t>(slots) * kWave);
+  S.val.resize(static_cast<size_t>(slots) * kWave * planes);
+  parallel_for(chunks_of(ns, 64), [&](int ch, int) {
+    const int nch = chunks_of(ns, 64);
+    const int32_t s0 = static_cast<int32_t>(static_cast<int64_t>(ns) * ch / nch);
+    const int32_t s1 = static_cast<int32_t>(static_cast<int64_t>(ns) * (ch + 1) / nch);
+    for (int32_t s = s0; s < s1; ++s)
+      for (int32_t lane = 0; lane < kWave; ++lane) {
+        const int32_t q = s * kWave + lane;
+        int32_t k = 0, k1 = 0, i = -1;
+        if (q < n) {
+          i = order[q];
+          k = rp[i];
+          k1 = rp[i + 1];
+        }
+        for (int32_t t = S.sp[s]; t < S.sp[s + 1]; ++t) {
+          while (k < k1 && !keep(i, col[k])) ++k;
+          const size_t e = static_cast<size_t>(t) * kWave + lane;
+          if (k < k1) {
+            S.col[e] = col[k];
+            for (int p = 0; p < planes; ++p)
+              S.val[(static_cast<size_t>(t) * planes + p) * kWave + lane] =
+                  static_cast<T>(src[static_cast<int64_t>(k) * stride + p]);
+            ++k;
+          } else {
+            S.col[e] = kPadCol;
+            for (int p = 0; p < planes; ++p) S.val[(static_cast<size_t>(t) * planes + p) * kWave + lane] = T(0);
+          }
+        }
+      }
+  });
+  return S;
+}
+
 }  // namespace
 
 template <typename T>
@@ -312,8 +388,14 @@ class Precond final : public PrecondBase {
   Precond(const cpr_params& prm, int32_t n_b, const std::vector<HostLevel>& hl, const std::vector<double>& lu,
           const std::vector<int32_t>& piv, const std::vector<int32_t>& bperm, const std::vector<int32_t>& bcoff,
           const HostVec<int32_t>& h_row_ptr, const HostVec<int32_t>& h_col,
-          const std::vector<int32_t>& bcolour, const double* d_vals_in, hipStream_t s)
-      : pre_(prm.pre_sweeps), post_(prm.post_sweeps), n_b_(n_b) {
+          const std::vector<int32_t>& bcolour, const double* d_vals_in, const HostBilu* bilu, const double* d_w,
+          hipStream_t s)
+      : pre_(prm.pre_sweeps),
+        post_(prm.post_sweeps),
+        n_b_(n_b),
+        bilu_(bilu != nullptr),
+        pgs_no_(prm.smoother == 1),
+        chunks_(prm.smoother_chunks) {
     const int nl = static_cast<int>(hl.size());
     lv_.resize(nl);
     const double sv = sizeof(T);
@@ -324,7 +406,8 @@ class Precond final : public PrecondBase {
       HostVec<int64_t> pos, diag_pos;  // written in full below
       std::vector<double> bytes;
     };
-    auto stage2_task = std::async(std::launch::async, [&]() {
+    std::future<Stage2Image> stage2_task;
+    if (!bilu_) stage2_task = std::async(std::launch::async, [&]() {
       Stage2Image S;
       const int32_t n = n_b;
       const int32_t ns = (n + kWave - 1) / kWave;
@@ -368,7 +451,9 @@ class Precond final : public PrecondBase {
     const size_t lds_limit = tail_lds_limit();
     auto lds_for = [&](int first, int staged) { return tail_layout<T>(hl, first, staged).lds_bytes; };
     tail_ = nl - 1;
-    if (prm.tail_nnz > 0)
+    // the one-workgroup tail runs PGS-SCM sweeps; PGS-NO keeps every smoothed
+    // level on its own kernels
+    if (prm.tail_nnz > 0 && !pgs_no_)
       while (tail_ > 0 && hl[tail_ - 1].A.nnz() <= prm.tail_nnz && lds_for(tail_ - 1, nl) <= lds_limit) --tail_;
     if (lds_for(tail_, nl) > lds_limit)
       throw Error(CPR_ERR_INVALID_ARG, "the coarsest level does not fit one workgroup's LDS (lower coarse_max)");
@@ -396,7 +481,8 @@ class Precond final : public PrecondBase {
         const HostLevel& H = hl[l];
         const bool in_tail = l >= tail_;
         const int32_t n = H.A.n_rows;
-        I.A = build_mat<T>(H.A, H.perm, inv[l], prm.row_layout, in_tail);
+        // PGS-NO walks rows in natural order from CSR row pointers
+        I.A = build_mat<T>(H.A, H.perm, inv[l], prm.row_layout, in_tail || pgs_no_);
         I.diag.resize(n);
         const int nch = chunks_of(n, 4096);
         parallel_for(nch, [&](int ch, int) {
@@ -551,10 +637,23 @@ class Precond final : public PrecondBase {
     tail_bytes_ += 8.0 * nL_ * nL_;
 
     const double t_levels = clock_ms();
+    const int32_t n = n_b;
+    pe_ = ar_.alloc<T>(n);
+    if (d_w) {
+      wt_ = ar_.alloc<T>(static_cast<int64_t>(9) * n);
+      launch_copy_cast<double, T>(static_cast<int64_t>(9) * n, d_w, wt_, s);
+      wv_ = ar_.alloc<double>(static_cast<int64_t>(3) * n);
+    }
+    if (bilu_) {
+      build_bilu(*bilu, h_row_ptr, h_col);
+      if (std::getenv("CPR_SETUP_TRACE"))
+        std::fprintf(stderr, "[cpr setup] device images: levels %.1f ms, block ILU(0) images %.1f\n",
+                     t_levels - t_start, clock_ms() - t_levels);
+      return;
+    }
     // ---- fine level for stage 2: cells in block-colour order
     bcoff_ = bcoff;
     cell_ = ar_.upload(bperm);
-    const int32_t n = n_b;
     Stage2Image S2 = stage2_task.get();
     const double t_s2wait = clock_ms();
     std::vector<int32_t>& sp = S2.sp;
@@ -581,7 +680,6 @@ class Precond final : public PrecondBase {
     HIPCHK(hipMemcpyAsync(&sing, d_sing, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (sing) throw Error(CPR_ERR_SINGULAR_BLOCK, "a 3x3 diagonal block is singular");
-    pe_ = ar_.alloc<T>(n);
     if (std::getenv("CPR_SETUP_TRACE"))
       std::fprintf(stderr,
                    "[cpr setup] device images: levels %.1f ms (waiting for host images %.1f), stage-2 image wait "
@@ -589,19 +687,26 @@ class Precond final : public PrecondBase {
                    t_levels - t_start, t_wait, t_s2wait - t_levels, clock_ms() - t_s2wait);
   }
 
-  void apply(const double* v, void* zv, hipStream_t s) override {
+  void apply(const double* v_in, void* zv, hipStream_t s) override {
     T* z = static_cast<T*>(zv);
+    const double* v = v_in;
+    if (wt_) {  // decoupled rows: B acts on W v
+      launch_block_gemv<T>(n_b_, wt_, v_in, wv_, s);
+      v = wv_;
+    }
     Level& L0 = lv_[0];
     const ZeroStart<T> zs = zero_start(0);
     launch_restrict_pressure<T>(L0.n, v, L0.perm, L0.b, zs, s);
     vcycle(0, s, zs.n_first > 0);
     launch_scatter<T>(L0.n, L0.x, L0.perm, pe_, s);
-    const SellView<T> F = fine_.view();
-    for (size_t c = 0; c + 1 < bcoff_.size(); ++c) {
-      if (timer) timer->begin(CPR_KSTAT_STAGE2, s);
-      launch_stage2<T>(F, bcoff_[c], bcoff_[c + 1], cell_, dinv_, dinv_ld_, v, pe_, z, s);
-      if (timer) timer->end(CPR_KSTAT_STAGE2, s, stage2_bytes_[c]);
-    }
+    second_stage(v, z, s);
+  }
+
+  void second_stage_own(const double* v, const double* pe, double* z, hipStream_t s) override {
+    launch_copy_cast<double, T>(n_b_, pe, pe_, s);
+    T* zt = sizeof(T) == sizeof(double) ? reinterpret_cast<T*>(z) : work_z();
+    second_stage(v, zt, s);
+    if (sizeof(T) != sizeof(double)) launch_copy_cast<T, double>(3 * static_cast<int64_t>(n_b_), zt, z, s);
   }
 
   void vcycle_own(const double* r, double* e, hipStream_t s) override {
@@ -630,11 +735,108 @@ class Precond final : public PrecondBase {
   int64_t bytes() const override { return ar_.bytes(); }
 
  private:
+  // z = Pi_P pe_ + R (v - A Pi_P pe_), R = multi-colour block Gauss-Seidel
+  // (fused per colour) or block ILU(0) (level-scheduled solves).
+  void second_stage(const double* v, T* z, hipStream_t s) {
+    if (bilu_) {
+      const SellView<T> R = fres_.view(), Lo = flow_.view(), U = bup_.view();
+      if (timer) timer->begin(CPR_KSTAT_STAGE2, s);
+      launch_bilu_residual<T>(R, v, pe_, rv_, s);
+      if (timer) timer->end(CPR_KSTAT_STAGE2, s, rbytes_);
+      for (size_t l = 0; l + 1 < flev_off_.size(); ++l) {
+        if (timer) timer->begin(CPR_KSTAT_STAGE2, s);
+        launch_bilu_forward<T>(flev_off_[l], flev_off_[l + 1], Lo, frow_, rv_, yv_, s);
+        if (timer) timer->end(CPR_KSTAT_STAGE2, s, fbytes_[l]);
+      }
+      for (size_t l = 0; l + 1 < blev_off_.size(); ++l) {
+        if (timer) timer->begin(CPR_KSTAT_STAGE2, s);
+        launch_bilu_backward<T>(blev_off_[l], blev_off_[l + 1], U, buinv_, n_b_, brow_, yv_, pe_, dv_, z, s);
+        if (timer) timer->end(CPR_KSTAT_STAGE2, s, bbytes_[l]);
+      }
+      return;
+    }
+    const SellView<T> F = fine_.view();
+    for (size_t c = 0; c + 1 < bcoff_.size(); ++c) {
+      if (timer) timer->begin(CPR_KSTAT_STAGE2, s);
+      launch_stage2<T>(F, bcoff_[c], bcoff_[c + 1], cell_, dinv_, dinv_ld_, v, pe_, z, s);
+      if (timer) timer->end(CPR_KSTAT_STAGE2, s, stage2_bytes_[c]);
+    }
+  }
+
+  T* work_z() {
+    if (!zbuf_) zbuf_ = ar_.alloc<T>(3 * static_cast<int64_t>(n_b_));
+    return zbuf_;
+  }
+
+  // Device images of the block ILU(0) second stage: the residual reads column
+  // 0 of every block, rows in natural order; the forward solve the lower
+  // factor blocks, rows in forward-level order; the backward solve the upper
+  // factor blocks and the inverted pivot blocks, rows in backward-level order.
+  void build_bilu(const HostBilu& F, const HostVec<int32_t>& rp, const HostVec<int32_t>& col) {
+    const int32_t n = n_b_;
+    const double sv = sizeof(T);
+    std::vector<int32_t> forder, border;
+    level_order(F.flev, F.n_flev, forder, flev_off_);
+    level_order(F.blev, F.n_blev, border, blev_off_);
+    auto up = [&](const BlockSellHost<T>& H, DevSell<T>& D) {
+      D.n_rows = n;
+      D.slots = H.sp.empty() ? 0 : H.sp.back();
+      D.slice_ptr = ar_.upload(H.sp);
+      D.col = ar_.upload(H.col);
+      D.val = ar_.upload(H.val);
+    };
+    {
+      std::vector<int32_t> natural(n);
+      std::iota(natural.begin(), natural.end(), 0);
+      auto R = build_block_sell<T>(natural, rp, col, F.acol0.data(), 3, 3, [](int32_t, int32_t) { return true; });
+      up(R, fres_);
+    }
+    {
+      auto L = build_block_sell<T>(forder, rp, col, F.lu.data(), 9, 9, [](int32_t i, int32_t j) { return j < i; });
+      up(L, flow_);
+    }
+    {
+      auto U = build_block_sell<T>(border, rp, col, F.lu.data(), 9, 9, [](int32_t i, int32_t j) { return j > i; });
+      up(U, bup_);
+    }
+    HostVec<T> ui(static_cast<size_t>(9) * n);
+    for (int32_t q = 0; q < n; ++q)
+      for (int e = 0; e < 9; ++e) ui[static_cast<size_t>(e) * n + q] = static_cast<T>(F.uinv[9 * static_cast<size_t>(border[q]) + e]);
+    buinv_ = ar_.upload(ui);
+    frow_ = ar_.upload(forder);
+    brow_ = ar_.upload(border);
+    rv_ = ar_.alloc<T>(3 * static_cast<int64_t>(n));
+    yv_ = ar_.alloc<T>(3 * static_cast<int64_t>(n));
+    dv_ = ar_.alloc<T>(3 * static_cast<int64_t>(n));
+    // algorithmic bytes per level launch: row index, blocks read, vectors
+    auto level_bytes = [&](const std::vector<int32_t>& order, const std::vector<int32_t>& off, bool fwd) {
+      std::vector<double> b(off.size() > 0 ? off.size() - 1 : 0, 0.0);
+      for (size_t l = 0; l + 1 < off.size(); ++l)
+        for (int32_t q = off[l]; q < off[l + 1]; ++q) {
+          const int32_t i = order[q];
+          double r = 4.0;
+          for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int32_t j = col[k];
+            if (fwd && j < i) r += 9.0 * sv + 4.0 + 3 * sv;   // L_ij, y_j
+            if (!fwd && j > i) r += 9.0 * sv + 4.0 + 3 * sv;  // U_ij, d_j
+          }
+          // forward: r_i in, y_i out; backward: Uinv_i, y_i, pe_i in, d_i, z_i out
+          r += fwd ? 6.0 * sv : 9.0 * sv + 3.0 * sv + sv + 6.0 * sv;
+          b[l] += r;
+        }
+      return b;
+    };
+    fbytes_ = level_bytes(forder, flev_off_, true);
+    bbytes_ = level_bytes(border, blev_off_, false);
+    // residual: column 0 of every block with its column, pe gathers, v in, r out
+    rbytes_ = static_cast<double>(rp[n]) * (3.0 * sv + 4.0 + sv) + 4.0 * n + 24.0 * n + 3.0 * sv * n;
+  }
+
   // The first pre-sweep of a level below the tail's start begins from x = 0;
   // its first colour is then fused into the kernel that writes the level's b.
   ZeroStart<T> zero_start(int l) const {
     ZeroStart<T> zs;
-    if (l < tail_ && pre_ > 0 && lv_[l].coff.size() > 1) {
+    if (!pgs_no_ && l < tail_ && pre_ > 0 && lv_[l].coff.size() > 1) {
       const Level& L = lv_[l];
       zs.n_first = L.coff[1];
       zs.diag = L.diag;
@@ -650,6 +852,16 @@ class Precond final : public PrecondBase {
     T* S[2] = {L.s0, L.s1};
     const MatView<T> A = L.A.view();
     const int kind = l == 0 ? CPR_KSTAT_SMOOTH_L0 : CPR_KSTAT_SMOOTH_COARSE;
+    if (pgs_no_) {  // sweep-start snapshot, then the chunked Gauss-Seidel
+      if (zero)
+        launch_fill<T>(L.n, (T)0, L.x, s);
+      else
+        launch_copy_cast<T, T>(L.n, L.x, L.s0, s);
+      if (timer) timer->begin(kind, s);
+      launch_gs_chunks<T>(A, L.diag, chunks_, L.b, L.x, zero ? nullptr : L.s0, s);
+      if (timer) timer->end(kind, s, L.colour_bytes.empty() ? 0.0 : L.colour_bytes[0]);
+      return;
+    }
     for (size_t c = first_done ? 1 : 0; c + 1 < L.coff.size(); ++c) {
       if (timer) timer->begin(kind, s);
       launch_gs_colour<T>(A, L.diag, L.coff[c], L.coff[c + 1], L.b, L.x, S[cur], S[cur ^ 1], zero, s);
@@ -714,6 +926,21 @@ class Precond final : public PrecondBase {
   int32_t dinv_ld_ = 0;
   T* pe_ = nullptr;
   std::vector<double> stage2_bytes_;
+  // block ILU(0) second stage
+  bool bilu_ = false;
+  std::vector<int32_t> flev_off_, blev_off_;
+  DevSell<T> fres_, flow_, bup_;
+  T* buinv_ = nullptr;
+  int32_t *frow_ = nullptr, *brow_ = nullptr;
+  T *rv_ = nullptr, *yv_ = nullptr, *dv_ = nullptr, *zbuf_ = nullptr;
+  std::vector<double> fbytes_, bbytes_;
+  double rbytes_ = 0.0;
+  // decoupling weights W (n x 9 in T) and W v
+  T* wt_ = nullptr;
+  double* wv_ = nullptr;
+  // PGS-NO smoother (natural order, chunked Gauss-Seidel)
+  bool pgs_no_ = false;
+  int32_t chunks_ = 1;
 };
 
 std::unique_ptr<PrecondBase> make_precond(bool fp32, const cpr_params& prm, int32_t n_b,
@@ -721,12 +948,13 @@ std::unique_ptr<PrecondBase> make_precond(bool fp32, const cpr_params& prm, int3
                                           const std::vector<int32_t>& piv, const std::vector<int32_t>& bperm,
                                           const std::vector<int32_t>& bcoff, const HostVec<int32_t>& h_row_ptr,
                                           const HostVec<int32_t>& h_col, const std::vector<int32_t>& bcolour,
-                                          const double* d_vals_in, hipStream_t s) {
+                                          const double* d_vals, const HostBilu* bilu, const double* d_w,
+                                          hipStream_t s) {
   if (fp32)
     return std::make_unique<Precond<float>>(prm, n_b, hl, lu, piv, bperm, bcoff, h_row_ptr, h_col, bcolour,
-                                            d_vals_in, s);
+                                            d_vals, bilu, d_w, s);
   return std::make_unique<Precond<double>>(prm, n_b, hl, lu, piv, bperm, bcoff, h_row_ptr, h_col, bcolour,
-                                           d_vals_in, s);
+                                           d_vals, bilu, d_w, s);
 }
 
 }  // namespace cpr

@@ -151,6 +151,26 @@ void cpr_handle::build_precond() {
   // test of the device inversion, made first so that no other SETUP step sees
   // a singular block).  67 MB come back to the host at 3.28M DOF instead of
   // the 534 MB of values.
+  // Decoupling: B is built on W A (computed here on the device, freed once
+  // the preconditioner holds its own images) and applied to W v.
+  Arena dec;
+  const double* d_vals_pc = d_vals_in;
+  double* d_w = nullptr;
+  if (prm.decoupling != 0) {
+    d_w = dec.alloc<double>(static_cast<int64_t>(n_b) * 9);
+    double* d_wa = dec.alloc<double>(static_cast<int64_t>(nnz_b) * 9);
+    int32_t* d_bad = dec.alloc<int32_t>(1);
+    int32_t bad = std::numeric_limits<int32_t>::max();
+    HIPCHK(hipMemcpyAsync(d_bad, &bad, sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    launch_decouple(n_b, d_rp_pat, d_col_pat, d_vals_in, prm.decoupling, d_w, d_wa, d_bad, stream);
+    HIPCHK(hipMemcpyAsync(&bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    if (bad != std::numeric_limits<int32_t>::max())
+      throw Error(CPR_ERR_SINGULAR_BLOCK,
+                  "the decoupling weights of cell " + std::to_string(bad) + " cannot be formed (singular diagonal block)");
+    d_vals_pc = d_wa;
+  }
+
   HostVec<double> pval(nnz_b);
   HostVec<uint8_t> nonzero(nnz_b);
   int32_t bad_row = std::numeric_limits<int32_t>::max();
@@ -160,7 +180,7 @@ void cpr_handle::build_precond() {
     uint8_t* d_nonzero = scratch.alloc<uint8_t>(nnz_b);
     int32_t* d_bad = scratch.alloc<int32_t>(1);
     HIPCHK(hipMemcpyAsync(d_bad, &bad_row, sizeof(int32_t), hipMemcpyHostToDevice, stream));
-    launch_setup_values(n_b, d_rp_pat, d_col_pat, d_vals_in, d_pval, d_nonzero, d_bad, stream);
+    launch_setup_values(n_b, d_rp_pat, d_col_pat, d_vals_pc, d_pval, d_nonzero, d_bad, stream);
     HIPCHK(hipMemcpyAsync(pval.data(), d_pval, pval.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
     HIPCHK(hipMemcpyAsync(nonzero.data(), d_nonzero, nonzero.size(), hipMemcpyDeviceToHost, stream));
     HIPCHK(hipMemcpyAsync(&bad_row, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
@@ -172,8 +192,31 @@ void cpr_handle::build_precond() {
   // The colourings depend only on each level's matrix and strength mask, not
   // on the coarsening that follows, so they run on threads of their own while
   // the levels are built: first the stage-2 block colouring (theta = 0 on the
-  // block graph: every stored nonzero off-diagonal block couples two cells).
-  auto block_task = std::async(std::launch::async, [this, &nonzero]() {
+  // block graph: every stored nonzero off-diagonal block couples two cells),
+  // or, for the block ILU(0) second stage, the factorisation.
+  const bool use_bilu = prm.second_stage == 1;
+  std::future<HostBilu> bilu_task;
+  if (use_bilu)
+    bilu_task = std::async(std::launch::async, [this, d_vals_pc]() {
+      HostBilu F;
+      F.lu.resize(static_cast<size_t>(nnz_b) * 9);
+      {
+        std::lock_guard<std::mutex> lk(device_api_mutex());
+        HIPCHK(hipMemcpy(F.lu.data(), d_vals_pc, F.lu.size() * sizeof(double), hipMemcpyDeviceToHost));
+      }
+      F.acol0.resize(static_cast<size_t>(nnz_b) * 3);
+      for (int64_t k = 0; k < nnz_b; ++k)
+        for (int r = 0; r < 3; ++r) F.acol0[3 * k + r] = F.lu[9 * k + 3 * r];
+      F.n_flev = bilu_forward_levels(n_b, h_row_ptr.data(), h_col.data(), F.flev);
+      F.n_blev = bilu_backward_levels(n_b, h_row_ptr.data(), h_col.data(), F.blev);
+      F.uinv.resize(static_cast<size_t>(n_b) * 9);
+      const int32_t bad = bilu0_factor(n_b, h_row_ptr.data(), h_col.data(), F.flev, F.lu.data(), F.uinv.data());
+      if (bad >= 0)
+        throw Error(CPR_ERR_SINGULAR_BLOCK, "block ILU(0) pivot block of cell " + std::to_string(bad) + " is singular");
+      return F;
+    });
+  auto block_task = std::async(std::launch::async, [this, &nonzero, use_bilu]() {
+    if (use_bilu) return Colouring{};
     Pattern B;
     B.n = n_b;
     B.ptr.assign(n_b + 1, 0);
@@ -266,7 +309,16 @@ void cpr_handle::build_precond() {
   const int nl = static_cast<int>(hl.size());
   for (int l = 0; l < nl; ++l) {
     HostLevel& L = hl[l];
-    if (l + 1 < nl) {
+    if (l + 1 < nl && prm.smoother == 1) {
+      // PGS-NO: rows stay in natural order, one class holding them all
+      (void)level_tasks[l].get();
+      const int32_t n = L.A.n_rows;
+      L.colour.assign(n, 0);
+      L.n_colours = 1;
+      L.perm.resize(n);
+      std::iota(L.perm.begin(), L.perm.end(), 0);
+      L.coff = {0, n};
+    } else if (l + 1 < nl) {
       Colouring c = level_tasks[l].get();
       L.colour = std::move(c.colour);
       L.n_colours = c.n_colours;
@@ -287,20 +339,24 @@ void cpr_handle::build_precond() {
   std::vector<int32_t> piv;
   if (!dense_lu(nc, lu, piv)) throw Error(CPR_ERR_SINGULAR_COARSE, "coarsest matrix is singular");
 
-  // stage-2 block colouring (computed on its own thread since the start)
+  // stage-2 block colouring or factorisation (computed on its own thread since the start)
   Colouring bc = block_task.get();
+  HostBilu bf;
+  if (use_bilu) bf = bilu_task.get();
   const double t_colour_wait = now_ms() - tp;
   tp = now_ms();
   std::vector<int32_t> bperm = std::move(bc.perm), bcoff = std::move(bc.coff);
 
   std::unique_ptr<PrecondBase> npc = make_precond(prm.precond_fp32 != 0, prm, n_b, hl, lu, piv, bperm, bcoff,
-                                                  h_row_ptr, h_col, bc.colour, d_vals_in, stream);
+                                                  h_row_ptr, h_col, bc.colour, d_vals_pc, use_bilu ? &bf : nullptr,
+                                                  d_w, stream);
   npc->timer = &prof;
   HIPCHK(hipStreamSynchronize(stream));
   pc = std::move(npc);
   this->hl.swap(hl);
   block_colour = std::move(bc.colour);
   n_block_colours = bc.n_colours;
+  bilu_host = std::move(bf);
   values_changed = false;
   last_setup_ms = now_ms() - t0;
   if (std::getenv("CPR_SETUP_TRACE"))

@@ -99,6 +99,17 @@ struct HostLevel {
   std::vector<int32_t> coff;  // colour offsets in device order
 };
 
+// Host products of the block ILU(0) second stage (kept for inspection): the
+// factors in the input block order (lu: L_ik for k < i, U_ij for j >= i;
+// uinv: inverted pivot blocks), the forward and backward level of every row,
+// and column 0 of every block of the matrix B is built on (the CPR residual
+// r = v - A Pi_P e only reads that column).
+struct HostBilu {
+  HostVec<double> lu, uinv, acol0;
+  std::vector<int32_t> flev, blev;
+  int32_t n_flev = 0, n_blev = 0;
+};
+
 // Event timing of kernel classes.
 class Profiler : public LaunchTimer {
  public:
@@ -132,19 +143,26 @@ class PrecondBase {
   virtual void apply(const double* v, void* z, hipStream_t s) = 0;
   virtual void vcycle_own(const double* r, double* e, hipStream_t s) = 0;
   virtual void smooth_own(int level, double* x, const double* b, int sweeps, bool zero_start, hipStream_t s) = 0;
+  // z = Pi_P pe + R (v - A Pi_P pe): the second stage of Algorithm "CPR method"
+  // given the stage-1 pressure correction pe (FP64 in, FP64 out; n_b and 3 n_b)
+  virtual void second_stage_own(const double* v, const double* pe, double* z, hipStream_t s) = 0;
   virtual int n_levels() const = 0;
   virtual bool fp32() const = 0;
   virtual int64_t bytes() const = 0;
   LaunchTimer* timer = nullptr;
 };
 
+// d_vals: the 3x3 blocks B is built on (device, input order; W A when the
+// rows are decoupled, then d_w holds W, n x 9 FP64, else null); bilu: the
+// block ILU(0) factors when the second stage is block ILU(0), else null (then
+// bperm/bcoff/bcolour give the block colouring of the Gauss-Seidel stage).
 std::unique_ptr<PrecondBase> make_precond(bool fp32, const cpr_params& prm, int32_t n_b,
                                           const std::vector<HostLevel>& hl,
                                           const std::vector<double>& lu, const std::vector<int32_t>& piv,
                                           const std::vector<int32_t>& bperm, const std::vector<int32_t>& bcoff,
                                           const HostVec<int32_t>& h_row_ptr, const HostVec<int32_t>& h_col,
-                                          const std::vector<int32_t>& bcolour, const double* d_vals_in,
-                                          hipStream_t s);
+                                          const std::vector<int32_t>& bcolour, const double* d_vals,
+                                          const HostBilu* bilu, const double* d_w, hipStream_t s);
 
 }  // namespace cpr
 
@@ -167,6 +185,7 @@ struct cpr_handle {
   std::vector<cpr::HostLevel> hl;
   std::vector<int32_t> block_colour;
   int32_t n_block_colours = 0;
+  cpr::HostBilu bilu_host;  // block ILU(0) factors (second_stage 1)
 
   // Krylov workspace (FP64 except Z in FP32 mode): the bases V and Z, the
   // residual r, and the scalars and partial sums of the handle's own solves

@@ -31,6 +31,10 @@ class Params:
     use_graphs: bool = True
     tail_nnz: int = 30000
     row_layout: int = 0
+    second_stage: int = 0   # 0 block Gauss-Seidel, 1 block ILU(0)
+    decoupling: int = 0     # 0 none, 1 quasi-IMPES, 2 ABF
+    smoother: int = 0       # 0 PGS-SCM, 1 PGS-NO
+    smoother_chunks: int = 256
 
     def to_c(self) -> A.cpr_params:
         p = A.cpr_params()
@@ -168,6 +172,29 @@ class Solver:
         _check_device_vec(z, 3 * self.n_b, "z", self.device)
         A.check(self._lib.cpr_precond_apply(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(z.data_ptr())), self._h)
         return z
+
+    def second_stage(self, v, pe, z=None):
+        """z = Pi_P pe + R (v - A Pi_P pe) with the handle's second stage."""
+        torch = _torch()
+        _check_device_vec(v, 3 * self.n_b, "v", self.device)
+        _check_device_vec(pe, self.n_b, "pe", self.device)
+        z = torch.empty_like(v) if z is None else z
+        _check_device_vec(z, 3 * self.n_b, "z", self.device)
+        A.check(self._lib.cpr_second_stage(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(pe.data_ptr()),
+                                           C.c_void_p(z.data_ptr())), self._h)
+        return z
+
+    def bilu_factors(self):
+        """Host copies of the block ILU(0) factors: dict with lu [nnz,3,3],
+        uinv [n,3,3], flev, blev [n] and the two level counts."""
+        lu = np.empty((self.nnz_b, 3, 3))
+        uinv = np.empty((self.n_b, 3, 3))
+        flev = np.empty(self.n_b, dtype=np.int32)
+        blev = np.empty(self.n_b, dtype=np.int32)
+        nl = np.zeros(2, dtype=np.int32)
+        A.check(self._lib.cpr_bilu_factors(self._h, lu.ctypes.data, uinv.ctypes.data, flev.ctypes.data,
+                                           blev.ctypes.data, nl.ctypes.data), self._h)
+        return dict(lu=lu, uinv=uinv, flev=flev, blev=blev, n_flev=int(nl[0]), n_blev=int(nl[1]))
 
     def vcycle(self, r, e=None):
         torch = _torch()

@@ -330,13 +330,14 @@ def case_spe10_like(seed=1100, shape=(60, 220, 85), sigma=2.0, kz_ratio=0.1,
     return case
 
 
-def newton_sequence(n_steps=12, seed=1200, base_seed=1100, shape=(60, 220, 85), **kw):
-    """Yield (step, case, b): successive Jacobians with fixed pattern and +-5% drift."""
+def newton_sequence(n_steps=12, seed=1200, base_seed=1100, shape=(60, 220, 85), amp=0.05, **kw):
+    """Yield (step, case, b): successive Jacobians with fixed pattern and +-amp
+    (default 5%) multiplicative drift per step."""
     case, faces = case_spe10_like(seed=base_seed, shape=shape, return_faces=True, **kw)
     active = case.active
     for step in range(n_steps):
         if step > 0:
-            faces = drift_faces(faces, np.random.default_rng(seed + step))
+            faces = drift_faces(faces, np.random.default_rng(seed + step), amp=amp)
             case = assemble(shape, active, faces)
         b = rhs(case.ndof, seed + 100 + step)
         case.meta = dict(name=f"newton_step{step}", step=step)
