@@ -44,7 +44,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import amg, bilu, coloring
+from . import amg, bilu, coloring, uaamg
 from .sparse import Csr
 
 
@@ -227,6 +227,7 @@ class CprPreconditioner:
     bilu: bilu.BiluFactors | None = None  # set when the second stage is block ILU(0)
     bilu_levels: tuple | None = None      # (forward, backward) level of every row
     W: np.ndarray | None = None           # decoupling weights (B is built on W A)
+    cycle: str = "v"                      # "v": RS V-cycle; "amli": UA-AMG nonlinear AMLI-cycle
 
     def apply(self, v):
         """z = B v (Algorithm CPR method with x = 0)."""
@@ -235,7 +236,10 @@ class CprPreconditioner:
         if self.W is not None:
             v = block_gemv(self.W.astype(dt), v)
         rp = restrict_pressure(v)
-        e = amg.vcycle(self.amg, rp, 0, dt)
+        if self.cycle == "amli":
+            e = uaamg.kcycle(self.amg, rp, 0, dt)
+        else:
+            e = amg.vcycle(self.amg, rp, 0, dt)
         z = prolong_pressure(e.astype(dt))
         Ad = self.A if dt == np.float64 else Bsr(self.A.row_ptr, self.A.col, self.A.vals.astype(dt))
         r = bsr_residual(Ad, z, v)
@@ -247,23 +251,31 @@ class CprPreconditioner:
         return z
 
 
-def setup(A: Bsr, params: amg.AmgParams | None = None, dtype=np.float64,
+def setup(A: Bsr, params=None, dtype=np.float64,
           second_stage: str = "bgs", decoupling: str = "none") -> CprPreconditioner:
-    """SETUP of B.  second_stage: "bgs" (multi-colour block Gauss-Seidel) or
-    "bilu" (block ILU(0) with level-scheduled solves); decoupling: "none",
-    "quasi-impes" or "abf" (B is then built on W A and applied to W v)."""
+    """SETUP of B.  params: amg.AmgParams (classical RS AMG, V-cycle; the
+    default) or uaamg.UaParams (the paper's UA-AMG with pairwise matching and
+    the nonlinear AMLI-cycle); second_stage: "bgs" (multi-colour block
+    Gauss-Seidel) or "bilu" (block ILU(0) with level-scheduled solves);
+    decoupling: "none", "quasi-impes" or "abf" (B is then built on W A and
+    applied to W v)."""
     W = None
     if decoupling != "none":
         W = decoupling_weights(A, decoupling)
         A = left_blocks(W, A)
-    H = amg.build_hierarchy(pressure_matrix(A), params)
+    cycle = "amli" if isinstance(params, uaamg.UaParams) else "v"
+    if cycle == "amli":
+        H = uaamg.build_hierarchy(pressure_matrix(A), params)
+    else:
+        H = amg.build_hierarchy(pressure_matrix(A), params)
     Af = Bsr(A.row_ptr.copy(), A.col.copy(), A.vals.copy())
     if second_stage == "bilu":
         F = bilu.bilu0(Af)
         levels = (bilu.forward_levels(F.row_ptr, F.col), bilu.backward_levels(F.row_ptr, F.col))
         return CprPreconditioner(A=Af, amg=H, block_colours=[], Dinv=F.Uinv, dtype=dtype, bilu=F,
-                                 bilu_levels=levels, W=W)
+                                 bilu_levels=levels, W=W, cycle=cycle)
     if second_stage != "bgs":
         raise ValueError(second_stage)
     colours = coloring.vertices_grouping(A.n_b, block_graph(A))
-    return CprPreconditioner(A=Af, amg=H, block_colours=colours, Dinv=diag_inverses(A), dtype=dtype, W=W)
+    return CprPreconditioner(A=Af, amg=H, block_colours=colours, Dinv=diag_inverses(A), dtype=dtype, W=W,
+                             cycle=cycle)
