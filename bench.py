@@ -67,17 +67,32 @@ def cpu_baseline(workload, shape_full, gpu_its, n_full):
         t2 = time.perf_counter()
     per_it_cell = (t2 - t1) / max(res.iterations, 1) / case.n_b
     est_ms = per_it_cell * n_full * gpu_its * 1e3
-    return {
+    out = {
         "value": est_ms,
         "unit": "ms",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"oracle FP64 on the {shape[0]}x{shape[1]}x{shape[2]} slab of the same generator "
-                   f"({case.n_b} cells): setup {t1 - t0:.1f} s, solve {t2 - t1:.1f} s, {res.iterations} its; "
-                   f"value = solve time per iteration per cell x {n_full} cells x {gpu_its} GPU FP64 its"),
+        "extrapolated": True,
+        "sample": (f"EXTRAPOLATED: oracle FP64 on the {shape[0]}x{shape[1]}x{shape[2]} slab of the same generator "
+                   f"({case.n_b} cells) on this host, one thread: setup {t1 - t0:.1f} s, solve {t2 - t1:.1f} s, "
+                   f"{res.iterations} its; value = solve time per iteration per cell x {n_full} cells x "
+                   f"{gpu_its} GPU FP64 its"),
         "cpu": _cpu_name(),
         "os_cpu_count": os.cpu_count(),
     }
+    # the oracle's own full-size solve, measured once by the golden-record
+    # script (tests/golden), on the machine named there
+    gname = {"spe10": "oracle_fullsize_spe10.json", "channels": "oracle_fullsize_channels.json"}.get(workload)
+    gpath = os.path.join(ROOT, "tests", "golden", gname) if gname else None
+    if gpath and os.path.exists(gpath) and tuple(shape_full) == ((60, 220, 85) if workload == "spe10"
+                                                                else (200, 200, 100)):
+        with open(gpath) as f:
+            g = json.load(f)
+        out["full_size_measured"] = {"solve_ms": g["fp64"]["solve_s"] * 1e3, "setup_ms": g["fp64"]["setup_s"] * 1e3,
+                                     "iterations": g["fp64"]["iterations"], "cores": g.get("cores", 1),
+                                     "cpu": g.get("cpu"), "where": "build machine, recorded by "
+                                     "tests/golden/make_fullsize_golden.py"}
+    return out
 
 
 def _cpu_name():
@@ -99,38 +114,23 @@ def _gen_request(desc):
     return desc["req"], desc["case_id"], case.row_ptr, case.col, case.vals, b
 
 
-def serve_bench(args):
-    """Serving stream: Poisson arrivals of solve requests of mixed sizes.
-
-    Requests follow the serving-stream recipe (1e4-1e6 cells, random aspect,
-    30% repeat Newton steps of resident cases).  A saturation pass over the
-    first requests (all submitted at once) fixes the service rate; the timed
-    pass submits every request at Poisson arrival times with rate
-    lambda = 0.8 x saturated throughput and reports p50/p99 latency from
-    arrival to completion and the completed solves per second.  Requests are
-    generated before both passes.
-    """
-    import multiprocessing as mp
+def _serve_stream(args, pool, descs, n_sat):
+    """Run the serving stream `descs` (requests generated first by `pool`): a
+    saturation pass over the first n_sat requests (all submitted at once)
+    fixes the service rate; the timed pass submits every request at Poisson
+    arrival times with rate lambda = 0.8 x saturated throughput (or --rate)
+    and measures latency from arrival to completion."""
     import threading
 
     import numpy as np
-
-    from workloads import blackoil as bo
-
-    # worker processes are forked before anything touches the GPU
-    pool = mp.get_context("fork").Pool(processes=args.gen_procs)
-    descs = bo.serving_requests(n_req=args.requests, seed=1300)
-
-    import torch  # noqa: F401  (initialises the device in this process only)
 
     from paper_2201_01970_amd import Params, Server
 
     params = Params(precond_fp32=True)
     budget = int(args.budget_gb * (1 << 30))
 
-    def run_pass(sub_descs, rate, pregenerated=None):
+    def run_pass(sub_descs, rate, pregenerated):
         srv = Server(budget, args.slots, params)
-        it = pregenerated if pregenerated is not None else pool.imap(_gen_request, sub_descs, chunksize=1)
         rng = np.random.default_rng(1301)
         t0 = time.perf_counter()
         arrivals = []
@@ -160,7 +160,7 @@ def serve_bench(args):
         done_submitting = threading.Event()
         th = threading.Thread(target=waiter)
         th.start()
-        for req, case_id, rp, col, vals, b in it:
+        for req, case_id, rp, col, vals, b in pregenerated:
             if rate:
                 t_next += rng.exponential(1.0 / rate)
                 delay = t0 + t_next - time.perf_counter()
@@ -178,30 +178,25 @@ def serve_bench(args):
         srv.close()
         return results, arrivals, wall, stats
 
-    # every request is generated before the passes (≈ 65 GB of host memory for
-    # the 512-request stream), so that both measure the server, not the
-    # request generator (12 processes make ≈ 5.6 requests/s, a third of the
-    # server's saturated rate)
+    # every request is generated before the passes, so that both measure the
+    # server, not the request generator
     reqs = []
     for k, r in enumerate(pool.imap(_gen_request, descs, chunksize=1)):
         reqs.append(r)
         if (k + 1) % 64 == 0:
             print(f"[serve] generated {k + 1}/{len(descs)} requests", file=sys.stderr, flush=True)
-    n_sat = min(args.saturation_requests, len(descs))
+    n_sat = min(n_sat, len(descs))
     res_sat, _, wall_sat, _ = run_pass(descs[:n_sat], None, reqs[:n_sat])
     sat_rate = n_sat / wall_sat
     rate = args.rate if args.rate else 0.8 * sat_rate
     print(f"[serve] saturation: {n_sat} requests in {wall_sat:.1f}s = {sat_rate:.2f}/s; lambda = {rate:.2f}/s",
           file=sys.stderr, flush=True)
     res, arrivals, wall, stats = run_pass(descs, rate, reqs)
-    pool.close()
     lat = [info["latency_ms"] for info, _ in res.values()]
     ok = [info for info, _ in res.values() if info["status"] == "CPR_OK"]
     its = [info["iterations"] for info in ok]
     rel = [info["relres_true"] for info in ok]
-    out = {
-        "metric": "serving p50/p99 latency (arrival to completion), solves/s",
-        "value": _pct(lat, 0.5), "unit": "ms", "higher_is_better": False,
+    return {
         "p50_ms": _pct(lat, 0.5), "p90_ms": _pct(lat, 0.9), "p99_ms": _pct(lat, 0.99),
         "solves_per_s": len(ok) / wall, "lambda_per_s": rate, "saturated_per_s": sat_rate,
         "arrivals_per_s": (len(arrivals) - 1) / (arrivals[-1] - arrivals[0]) if len(arrivals) > 1 else None,
@@ -209,11 +204,29 @@ def serve_bench(args):
         "iterations_median": _pct(its, 0.5), "relres_true_max": max(rel) if rel else None,
         "rebuilt": sum(1 for info in ok if info["rebuilt"]),
         "server": stats, "slots": args.slots, "budget_gb": args.budget_gb,
-        "config": {"workload": "serving stream: 1e4-1e6 cells log-uniform, nz 2-50, aspect 1/4-4, "
-                               "sigma U[1,2.5], 30% repeat Newton steps (+-5% drift)",
-                   "precond": "fp32", "outer": "fp64 FGMRES(30)", "tol": args.tol},
-        "data": "synthetic",
+        "workload": "serving stream: 1e4-1e6 cells log-uniform, nz 2-50, aspect 1/4-4, sigma U[1,2.5], "
+                    "30% repeat Newton steps (+-5% drift); FP32 preconditioner, FP64 FGMRES(30)",
     }
+
+
+def serve_bench(args):
+    """Serving stream of args.requests requests (default 512): p50/p99 latency
+    from arrival to completion and solves/s at 0.8 x the saturated rate."""
+    import multiprocessing as mp
+
+    from workloads import blackoil as bo
+
+    # worker processes are forked before anything touches the GPU
+    pool = mp.get_context("fork").Pool(processes=args.gen_procs)
+    descs = bo.serving_requests(n_req=args.requests, seed=1300)
+
+    import torch  # noqa: F401  (initialises the device in this process only)
+
+    r = _serve_stream(args, pool, descs, args.saturation_requests)
+    pool.close()
+    out = {"metric": "serving p50/p99 latency (arrival to completion), solves/s", "value": r["p50_ms"], "unit": "ms",
+           "higher_is_better": False, **r, "config": {"workload": r.pop("workload"), "tol": args.tol},
+           "data": "synthetic"}
     print(json.dumps(out), flush=True)
 
 
@@ -280,6 +293,11 @@ def _params(args, **kw):
         kw.setdefault("smoother_chunks", args.chunks)
     if getattr(args, "theta_color", None) is not None:
         kw.setdefault("theta_color", args.theta_color)
+    if getattr(args, "amg", "rs") == "ua":
+        kw.setdefault("amg_kind", 1)
+        kw.setdefault("coarse_max", 10000)  # the paper's coarsest size
+    if getattr(args, "coarse_max", None) is not None:
+        kw["coarse_max"] = args.coarse_max
     return Params(**kw)
 
 
@@ -293,7 +311,10 @@ def _method_config(args):
     p = _params(args)
     smoother = ("PGS-SCM theta=%g" % p.theta_color if p.smoother == 0
                 else "PGS-NO %d chunks" % p.smoother_chunks)
-    return {"amg": f"RS theta=0.25, coarse<=50, {smoother}, 2+2 sweeps",
+    amg = (f"RS theta=0.25, V-cycle, coarse<={p.coarse_max}" if p.amg_kind == 0 else
+           f"UA-AMG {p.npair}x pairwise matching beta={p.pair_beta}, nonlinear AMLI-cycle ({p.amli_inner} GCR steps), "
+           f"coarse<={p.coarse_max} (explicit inverse)")
+    return {"amg": f"{amg}, {smoother}, 2+2 sweeps",
             "stage2": "multi-colour block GS" if p.second_stage == 0 else "block ILU(0), level-scheduled solves",
             "decoupling": {0: "none", 1: "quasi-IMPES", 2: "ABF"}[p.decoupling]}
 
@@ -490,6 +511,8 @@ def main():
                     help="run the theta / launch-shape / PGS-NO / mu experiment tables instead")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--saturation-requests", type=int, default=64)
+    ap.add_argument("--serve-leg", type=int, default=64,
+                    help="requests of the short serving leg added to the default line (0 = none)")
     ap.add_argument("--rate", type=float, default=0.0, help="arrival rate per second (default 0.8 x saturation)")
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--budget-gb", type=float, default=200.0)
@@ -502,6 +525,9 @@ def main():
     ap.add_argument("--smoother", choices=sorted(SMOOTHERS), default="pgs-scm")
     ap.add_argument("--chunks", type=int, default=None, help="PGS-NO chunks per level")
     ap.add_argument("--theta-color", type=float, default=None, help="colouring threshold of PGS-SCM")
+    ap.add_argument("--amg", choices=("rs", "ua"), default="rs",
+                    help="pressure AMG: Ruge-Stueben V-cycle or the paper's UA-AMG with the AMLI-cycle")
+    ap.add_argument("--coarse-max", type=int, default=None, help="coarsest AMG size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solve of one Jacobian is not "
@@ -516,6 +542,16 @@ def main():
     if args.experiments:
         experiments_bench(args)
         return
+
+    serve_pool = serve_descs = None
+    if args.serve_leg > 0:
+        # the request generators are forked before anything touches the GPU
+        import multiprocessing as mp
+
+        from workloads import blackoil as bo
+
+        serve_pool = mp.get_context("fork").Pool(processes=args.gen_procs)
+        serve_descs = bo.serving_requests(n_req=args.serve_leg, seed=1300)
 
     import numpy as np
     import torch
@@ -635,8 +671,8 @@ def main():
         "config": {"workload": workload, "n_cells": case.n_b, "dof": case.ndof, "nnz_blocks": case.nnz_b,
                    "tol": args.tol, "krylov": "FGMRES(30)", **_method_config(args),
                    "tail_nnz": _params(args).tail_nnz, "row_layout": _params(args).row_layout},
-        "p50_ms": _pct(r32["times"], 0.5),
-        "p99_ms": _pct(r32["times"], 0.99),
+        "solve_p50_ms": _pct(r32["times"], 0.5),
+        "solve_p99_ms": _pct(r32["times"], 0.99),
         "iterations_fp32": r32["info"]["iterations"],
         "relres_true_fp32": r32["info"]["relres_true"],
         "setup_s_fp32": r32["setup_s"],
@@ -652,6 +688,15 @@ def main():
         out.update({"fp64_ms": med64, "fp64_p99_ms": _pct(r64["times"], 0.99),
                     "iterations_fp64": r64["info"]["iterations"], "relres_true_fp64": r64["info"]["relres_true"],
                     "setup_s_fp64": r64["setup_s"], "speedup_fp32_vs_fp64": med64 / med32})
+    if serve_pool is not None:
+        sv = _serve_stream(args, serve_pool, serve_descs, max(8, args.serve_leg // 4))
+        serve_pool.close()
+        out["serving"] = sv
+        out["p50_ms"] = sv["p50_ms"]
+        out["p99_ms"] = sv["p99_ms"]
+        out["solves_per_s"] = sv["solves_per_s"]
+        print(f"[bench] serving {sv['requests']} requests: p50 {sv['p50_ms']:.0f} ms p99 {sv['p99_ms']:.0f} ms "
+              f"{sv['solves_per_s']:.1f} solves/s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         its = r64["info"]["iterations"] if r64 else r32["info"]["iterations"]
         out["cpu_baseline"] = cpu_baseline(args.workload, shape, its, case.n_b)

@@ -110,6 +110,18 @@ typedef struct {
                              as they were when the sweep started [0] */
   int32_t smoother_chunks;/* chunks of the PGS-NO smoother on every level (rows per
                              chunk = ceil(n / chunks)) [256] */
+  int32_t amg_kind;       /* pressure solver B_P: 0 = classical Ruge-Stueben AMG
+                             (theta_rs), V-cycle; 1 = the paper's unsmoothed
+                             aggregation AMG (Section 6): npair passes of pairwise
+                             matching with threshold pair_beta per level, and the
+                             nonlinear AMLI-cycle, whose coarse corrections are
+                             amli_inner steps of flexible GCR preconditioned by the next
+                             level's cycle; the coarsest level (coarse_max rows, the
+                             paper uses 10000) is solved directly by its inverse,
+                             formed on the GPU at SETUP [0] */
+  int32_t amli_inner;     /* flexible GCR steps per coarse correction, 1 or 2 [2] */
+  int32_t npair;          /* pairwise matching passes per level [2] */
+  double pair_beta;       /* strong-coupling threshold of the matching [0.25] */
 } cpr_params;
 
 typedef struct {

@@ -71,6 +71,11 @@ cpr_status cpr_level_arrays(const cpr_handle* h, int32_t level, int32_t* row_ptr
 cpr_status cpr_level_interp(const cpr_handle* h, int32_t level, int32_t* row_ptr, int32_t* col,
                             double* val);
 
+/* Aggregate of every row of level `level` (int32[n_l], numbered in formation
+ * order) when the pressure solver is the aggregation AMG (amg_kind 1).
+ * CPR_ERR_INVALID_ARG for the coarsest level or a Ruge-Stueben hierarchy. */
+cpr_status cpr_level_aggregates(const cpr_handle* h, int32_t level, int32_t* agg);
+
 /* Colour of every cell in the stage-2 block colouring (int32[n_block_rows]). */
 cpr_status cpr_block_colours(const cpr_handle* h, int32_t* colour);
 
@@ -111,6 +116,13 @@ cpr_status cpr_host_interpolation(int32_t n, const int32_t* a_ptr, const int32_t
 cpr_status cpr_host_galerkin(int32_t n, int32_t n_coarse, const int32_t* a_ptr, const int32_t* a_col,
                              const double* a_val, const int32_t* p_ptr, const int32_t* p_col,
                              const double* p_val, int32_t* c_ptr, int32_t* c_col, double* c_val);
+
+/* Aggregates of unsmoothed-aggregation AMG (the paper's NPAIR aggregation,
+ * Section 6): npair passes of non-symmetric pairwise matching with
+ * threshold beta on the CSR matrix A (rows sorted).  agg[n] receives the
+ * aggregate of every row (numbered in formation order), *n_agg their count. */
+cpr_status cpr_host_aggregates(int32_t n, const int32_t* a_ptr, const int32_t* a_col, const double* a_val,
+                               double beta, int32_t npair, int32_t* agg, int32_t* n_agg);
 
 /* Block ILU(0) (the second stage R of eq. (CPR) named in Section 3.1, with
  * the level scheduling of Section 6) of a 3x3-block matrix with sorted

@@ -69,6 +69,10 @@ class cpr_params(C.Structure):
         ("decoupling", C.c_int32),
         ("smoother", C.c_int32),
         ("smoother_chunks", C.c_int32),
+        ("amg_kind", C.c_int32),
+        ("amli_inner", C.c_int32),
+        ("npair", C.c_int32),
+        ("pair_beta", C.c_double),
     ]
 
 
@@ -134,10 +138,12 @@ SIGNATURES = {
     "cpr_level_arrays": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "cpr_level_interp": (_I32, [_P, _I32, _P, _P, _P]),
     "cpr_block_colours": (_I32, [_P, _P]),
+    "cpr_level_aggregates": (_I32, [_P, _I32, _P]),
     "cpr_host_grouping": (_I32, [_I32, _P, _P, _P, _P]),
     "cpr_host_rs_split": (_I32, [_I32, _P, _P, _P]),
     "cpr_host_interpolation": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "cpr_host_bilu0": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _P]),
+    "cpr_host_aggregates": (_I32, [_I32, _P, _P, _P, _D, _I32, _P, _P]),
     "cpr_host_galerkin": (_I32, [_I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "cpr_profile_enable": (_I32, [_P, _I32]),
     "cpr_profile_read": (_I32, [_P, _I32, _P, _P, _P]),

@@ -29,6 +29,7 @@ SOURCES = [
     "noalloc.hip",
     "kernels_bilu.hip",
     "kernels_decouple.hip",
+    "kernels_amli.hip",
 ]
 
 ARCH = os.environ.get("CPR_OFFLOAD_ARCH", "gfx950")

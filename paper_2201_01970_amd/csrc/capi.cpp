@@ -157,6 +157,10 @@ void cpr_params_default(cpr_params* p) {
   p->decoupling = 0;
   p->smoother = 0;
   p->smoother_chunks = 256;
+  p->amg_kind = 0;
+  p->amli_inner = 2;
+  p->npair = 2;
+  p->pair_beta = 0.25;
 }
 
 cpr_status cpr_setup(const cpr_bsr* A, const cpr_params* p, void* hip_stream, cpr_handle** out) {
@@ -174,7 +178,9 @@ cpr_status cpr_setup(const cpr_bsr* A, const cpr_params* p, void* hip_stream, cp
         !(prm.row_layout == 0 || prm.row_layout == 1 || prm.row_layout == 2 || prm.row_layout == 4 ||
           prm.row_layout == 16 || prm.row_layout == 32 || prm.row_layout == 64) ||
         prm.second_stage < 0 || prm.second_stage > 1 || prm.decoupling < 0 || prm.decoupling > 2 ||
-        prm.smoother < 0 || prm.smoother > 1 || prm.smoother_chunks < 1)
+        prm.smoother < 0 || prm.smoother > 1 || prm.smoother_chunks < 1 || prm.amg_kind < 0 || prm.amg_kind > 1 ||
+        prm.amli_inner < 1 || prm.amli_inner > 2 || prm.npair < 1 || prm.npair > 4 || !(prm.pair_beta >= 0.0) ||
+        (prm.amg_kind == 1 && prm.smoother != 0))
       throw Error(CPR_ERR_INVALID_ARG, "invalid parameters");
     h = new cpr_handle();
     h->prm = prm;
@@ -429,6 +435,13 @@ cpr_status cpr_level_interp(const cpr_handle* h, int32_t level, int32_t* row_ptr
   return CPR_OK;
 }
 
+cpr_status cpr_level_aggregates(const cpr_handle* h, int32_t level, int32_t* agg) {
+  if (!h || !agg || level < 0 || level >= static_cast<int32_t>(h->hl.size()) || h->hl[level].agg.empty())
+    return fail(const_cast<cpr_handle*>(h), CPR_ERR_INVALID_ARG, "level has no aggregates");
+  std::copy(h->hl[level].agg.begin(), h->hl[level].agg.end(), agg);
+  return CPR_OK;
+}
+
 cpr_status cpr_block_colours(const cpr_handle* h, int32_t* colour) {
   if (!h || !colour) return fail(const_cast<cpr_handle*>(h), CPR_ERR_INVALID_ARG, "null argument");
   std::copy(h->block_colour.begin(), h->block_colour.end(), colour);
@@ -527,6 +540,19 @@ cpr_status cpr_host_galerkin(int32_t n, int32_t n_coarse, const int32_t* a_ptr, 
     std::copy(C.ptr.begin(), C.ptr.end(), c_ptr);
     if (c_col) std::copy(C.col.begin(), C.col.end(), c_col);
     if (c_val) std::copy(C.val.begin(), C.val.end(), c_val);
+    return CPR_OK;
+  });
+}
+
+cpr_status cpr_host_aggregates(int32_t n, const int32_t* a_ptr, const int32_t* a_col, const double* a_val,
+                               double beta, int32_t npair, int32_t* agg, int32_t* n_agg) {
+  if (n < 0 || !a_ptr || !a_col || !a_val || !agg || !n_agg || npair < 1)
+    return fail(nullptr, CPR_ERR_INVALID_ARG, "invalid argument");
+  return guarded(nullptr, [&]() -> cpr_status {
+    const HostCsr A = make_csr(n, n, a_ptr, a_col, a_val);
+    std::vector<int32_t> a;
+    *n_agg = npair_aggregates(A, beta, npair, a);
+    std::copy(a.begin(), a.end(), agg);
     return CPR_OK;
   });
 }

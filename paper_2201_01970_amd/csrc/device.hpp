@@ -115,6 +115,35 @@ template <typename T>
 void launch_gs_chunks(const MatView<T>& A, const T* diag, int32_t n_chunks, const T* b, T* x, const T* snap,
                       hipStream_t s);
 
+// ---- nonlinear AMLI-cycle (aggregation AMG) ----
+// Dot-product grid of a level of n rows (partials: 2 * grid doubles).
+int amli_dot_grid(int64_t n);
+// part = partial sums of (x1, y1) and, if x2, of (x2, y2)
+template <typename T>
+void launch_gcr_dots(int64_t n, const T* x1, const T* y1, const T* x2, const T* y2, double* part, hipStream_t s);
+// alpha1 = (f,w1)/(w1,w1) from part; z1 = x; f -= alpha1 w1; scal = {alpha1, (w1,w1)}
+template <typename T>
+void launch_gcr_step1(int64_t n, const double* part, const T* x, T* z1, T* f, const T* w1, double* scal,
+                      hipStream_t s);
+// x = alpha1 x, alpha1 = (f,w1)/(w1,w1) from part (a single GCR step)
+template <typename T>
+void launch_gcr_single(int64_t n, const double* part, T* x, hipStream_t s);
+// beta = (w2,w1)/scal[1] from part; w2 -= beta w1; x -= beta z1; part2 = partials of (w2,w2), (r1,w2)
+template <typename T>
+void launch_gcr_orth(int64_t n, const double* part, const double* scal, T* w2, const T* w1, T* x, const T* z1,
+                     const T* r1, double* part2, hipStream_t s);
+// x = alpha1 z1 + alpha2 x, alpha2 = (r1,w2)/(w2,w2) from part2
+template <typename T>
+void launch_gcr_finish(int64_t n, const double* part2, const double* scal, T* x, const T* z1, hipStream_t s);
+// Gauss-Jordan step k on the row-major n x n matrix a (m: n scratch doubles;
+// piv[k] = pivot row; *bad = 1 when column k has no nonzero pivot)
+void launch_gj_step(int n, int k, double* a, int32_t* piv, double* m, int32_t* bad, hipStream_t s);
+// dst[i][j] = src[i][cols[j]] (n x n, row-major)
+void launch_permute_cols(int n, const double* src, const int32_t* cols, double* dst, hipStream_t s);
+// x = Ainv b (Ainv n x n FP64 row-major; b, x in T)
+template <typename T>
+void launch_dense_gemv(int n, const double* ainv, const T* b, T* x, hipStream_t s);
+
 // Decoupling (kind 1 quasi-IMPES, 2 ABF): w[9i..] = W_i from the diagonal
 // block of row i, wa[9k..] = W_i A_k for every stored block k of row i (FP64,
 // input order); *bad_row = min(*bad_row, i) for rows whose W_i cannot be formed.

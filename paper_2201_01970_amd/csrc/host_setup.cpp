@@ -782,4 +782,134 @@ int32_t bilu0_factor(int32_t n, const int32_t* rp, const int32_t* col, const std
   return first_bad == std::numeric_limits<int32_t>::max() ? -1 : first_bad;
 }
 
+// ------------------------------------------------------------ pairwise matching
+int32_t pairwise_matching(const HostCsr& A, double beta, std::vector<int32_t>& agg) {
+  const int32_t n = A.n_rows;
+  const HostCsr T = transpose(A);
+  // symmetric part: merge row i of A (a_ij) and of A^T (a_ji), columns ascending
+  std::vector<int64_t> sp(n + 1, 0);
+  std::vector<int32_t> sc;
+  std::vector<double> sv;
+  sc.reserve(A.col.size() * 2);
+  sv.reserve(A.col.size() * 2);
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t p = A.ptr[i], q = T.ptr[i];
+    const int32_t pe = A.ptr[i + 1], qe = T.ptr[i + 1];
+    while (p < pe || q < qe) {
+      const int32_t jp = p < pe ? A.col[p] : std::numeric_limits<int32_t>::max();
+      const int32_t jq = q < qe ? T.col[q] : std::numeric_limits<int32_t>::max();
+      const int32_t j = std::min(jp, jq);
+      const bool has_ij = jp == j, has_ji = jq == j;
+      const double h_ij = has_ij ? A.val[p] / 2.0 : 0.0;
+      const double h_ji = has_ji ? T.val[q] / 2.0 : 0.0;
+      if (has_ij) ++p;
+      if (has_ji) ++q;
+      if (j == i) continue;
+      // the half-entry of the lower-numbered row first
+      const bool lo_first = i < j;
+      const bool has_lo = lo_first ? has_ij : has_ji, has_hi = lo_first ? has_ji : has_ij;
+      const double h_lo = lo_first ? h_ij : h_ji, h_hi = lo_first ? h_ji : h_ij;
+      double acc = 0.0;
+      if (has_lo) acc = acc + h_lo;
+      if (has_hi) acc = acc + h_hi;
+      sc.push_back(j);
+      sv.push_back(acc);
+    }
+    sp[i + 1] = static_cast<int64_t>(sc.size());
+  }
+  // strong sets
+  std::vector<int64_t> Sp(n + 1, 0);
+  std::vector<int32_t> Sc;
+  std::vector<double> Sv;  // s_ij of each strong entry
+  for (int32_t i = 0; i < n; ++i) {
+    double top = 0.0;
+    bool any = false;
+    for (int64_t e = sp[i]; e < sp[i + 1]; ++e) {
+      const double v = -sv[e];
+      top = any ? std::max(top, v) : v;
+      any = true;
+    }
+    if (any && top > 0.0)
+      for (int64_t e = sp[i]; e < sp[i + 1]; ++e)
+        if (sv[e] < -beta * top) {
+          Sc.push_back(sc[e]);
+          Sv.push_back(sv[e]);
+        }
+    Sp[i + 1] = static_cast<int64_t>(Sc.size());
+  }
+  std::vector<int64_t> m(n, 0);
+  for (int32_t i = 0; i < n; ++i)
+    for (int64_t e = Sp[i]; e < Sp[i + 1]; ++e) m[Sc[e]] += 1;
+  using Entry = std::pair<int64_t, int32_t>;
+  std::priority_queue<Entry, std::vector<Entry>, std::greater<Entry>> heap;
+  for (int32_t i = 0; i < n; ++i) heap.push({m[i], i});
+  agg.assign(n, -1);
+  int32_t n_agg = 0;
+  while (!heap.empty()) {
+    const Entry top = heap.top();
+    heap.pop();
+    const int32_t i = top.second;
+    if (agg[i] >= 0 || top.first != m[i]) continue;
+    int32_t best = -1;
+    double best_v = 0.0;
+    for (int64_t e = Sp[i]; e < Sp[i + 1]; ++e) {
+      const int32_t j = Sc[e];
+      if (agg[j] >= 0) continue;
+      if (best < 0 || Sv[e] < best_v) {
+        best = j;
+        best_v = Sv[e];
+      }
+    }
+    const int32_t members[2] = {i, best};
+    const int nm = best < 0 ? 1 : 2;
+    for (int t = 0; t < nm; ++t) agg[members[t]] = n_agg;
+    for (int t = 0; t < nm; ++t)
+      for (int64_t e = Sp[members[t]]; e < Sp[members[t] + 1]; ++e) {
+        const int32_t k = Sc[e];
+        m[k] -= 1;
+        if (agg[k] < 0) heap.push({m[k], k});
+      }
+    ++n_agg;
+  }
+  return n_agg;
+}
+
+HostCsr aggregation_matrix(const std::vector<int32_t>& agg, int32_t n_agg) {
+  HostCsr P;
+  const int32_t n = static_cast<int32_t>(agg.size());
+  P.n_rows = n;
+  P.n_cols = n_agg;
+  P.ptr.resize(n + 1);
+  P.col.resize(n);
+  P.val.resize(n);
+  for (int32_t i = 0; i <= n; ++i) P.ptr[i] = i;
+  for (int32_t i = 0; i < n; ++i) {
+    P.col[i] = agg[i];
+    P.val[i] = 1.0;
+  }
+  return P;
+}
+
+int32_t npair_aggregates(const HostCsr& A, double beta, int npair, std::vector<int32_t>& agg) {
+  const int32_t n = A.n_rows;
+  agg.resize(n);
+  for (int32_t i = 0; i < n; ++i) agg[i] = i;
+  int32_t n_agg = n;
+  HostCsr Ak;
+  const HostCsr* cur = &A;
+  for (int pass = 0; pass < npair; ++pass) {
+    std::vector<int32_t> a;
+    const int32_t na = pairwise_matching(*cur, beta, a);
+    for (int32_t i = 0; i < n; ++i) agg[i] = a[agg[i]];
+    n_agg = na;
+    if (pass + 1 < npair) {
+      const HostCsr P = aggregation_matrix(a, na);
+      const HostCsr R = transpose(P);
+      Ak = spgemm_ordered(R, spgemm_ordered(*cur, P));
+      cur = &Ak;
+    }
+  }
+  return n_agg;
+}
+
 }  // namespace cpr

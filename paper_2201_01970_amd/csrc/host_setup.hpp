@@ -129,6 +129,24 @@ int32_t bilu_backward_levels(int32_t n, const int32_t* rp, const int32_t* col, s
 // block's largest entry.
 bool inverse3(const double* a, double* inv);
 
+// Pairwise matching (one pass) of unsmoothed-aggregation AMG (the paper's
+// NPAIR aggregation, Section 6).  Couplings s_ij = a_ij/2 + a_ji/2 (the half
+// of the lower-numbered row added first, a missing entry counting as 0);
+// S_i = {j != i : s_ij < -beta * max_k(-s_ik)} when that maximum is positive;
+// m_i = number of unaggregated rows k with i in S_k.  Repeatedly the
+// unaggregated row i of smallest m_i (ties: smallest index) is paired with its
+// unaggregated j in S_i of most negative s_ij (ties: smallest index), or left
+// alone; aggregates are numbered in formation order.  agg[i] = aggregate of
+// row i; returns the aggregate count.
+int32_t pairwise_matching(const HostCsr& A, double beta, std::vector<int32_t>& agg);
+
+// npair successive matching passes (the second on P_1^T A P_1, formed by
+// transpose and spgemm_ordered); agg composes the passes.
+int32_t npair_aggregates(const HostCsr& A, double beta, int npair, std::vector<int32_t>& agg);
+
+// The 0/1 prolongation of an aggregation (row i: a 1 in column agg[i]).
+HostCsr aggregation_matrix(const std::vector<int32_t>& agg, int32_t n_agg);
+
 // Host threads used by the row-parallel SETUP steps (at most 16).
 int setup_threads();
 

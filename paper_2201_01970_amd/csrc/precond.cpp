@@ -395,7 +395,9 @@ class Precond final : public PrecondBase {
         n_b_(n_b),
         bilu_(bilu != nullptr),
         pgs_no_(prm.smoother == 1),
-        chunks_(prm.smoother_chunks) {
+        chunks_(prm.smoother_chunks),
+        ua_(prm.amg_kind == 1),
+        inner_(prm.amli_inner) {
     const int nl = static_cast<int>(hl.size());
     lv_.resize(nl);
     const double sv = sizeof(T);
@@ -451,11 +453,13 @@ class Precond final : public PrecondBase {
     const size_t lds_limit = tail_lds_limit();
     auto lds_for = [&](int first, int staged) { return tail_layout<T>(hl, first, staged).lds_bytes; };
     tail_ = nl - 1;
-    // the one-workgroup tail runs PGS-SCM sweeps; PGS-NO keeps every smoothed
-    // level on its own kernels
-    if (prm.tail_nnz > 0 && !pgs_no_)
+    // the one-workgroup tail runs PGS-SCM sweeps of a V-cycle; PGS-NO keeps
+    // every smoothed level on its own kernels; the aggregation AMG's cycle
+    // has no tail (its coarsest level is solved by its inverse)
+    if (ua_) tail_ = nl;
+    if (prm.tail_nnz > 0 && !pgs_no_ && !ua_)
       while (tail_ > 0 && hl[tail_ - 1].A.nnz() <= prm.tail_nnz && lds_for(tail_ - 1, nl) <= lds_limit) --tail_;
-    if (lds_for(tail_, nl) > lds_limit)
+    if (!ua_ && lds_for(tail_, nl) > lds_limit)
       throw Error(CPR_ERR_INVALID_ARG, "the coarsest level does not fit one workgroup's LDS (lower coarse_max)");
     // the sweep matrices staged in LDS: as many levels, coarsest first, as fit
     int staged = nl - 1;
@@ -580,6 +584,8 @@ class Precond final : public PrecondBase {
     }
     nL_ = lv_.back().n;
     lu_ = ar_.upload(lu);
+    if (ua_) build_amli(s);  // coarsest inverse and the GCR buffers; no tail kernel
+    if (!ua_) {
     // compose the factorisation's row swaps: (P b)_i = b[rperm[i]]
     std::vector<int32_t> rperm(piv.size());
     std::iota(rperm.begin(), rperm.end(), 0);
@@ -635,6 +641,7 @@ class Precond final : public PrecondBase {
                      (L.nnz_r + L.nnz_p) * (sv + 4.0) + 4.0 * (L.n + lv_[l + 1].n) + 4.0 * L.n * sv;
     }
     tail_bytes_ += 8.0 * nL_ * nL_;
+    }
 
     const double t_levels = clock_ms();
     const int32_t n = n_b;
@@ -697,7 +704,7 @@ class Precond final : public PrecondBase {
     Level& L0 = lv_[0];
     const ZeroStart<T> zs = zero_start(0);
     launch_restrict_pressure<T>(L0.n, v, L0.perm, L0.b, zs, s);
-    vcycle(0, s, zs.n_first > 0);
+    cycle(0, s, zs.n_first > 0);
     launch_scatter<T>(L0.n, L0.x, L0.perm, pe_, s);
     second_stage(v, z, s);
   }
@@ -712,7 +719,7 @@ class Precond final : public PrecondBase {
   void vcycle_own(const double* r, double* e, hipStream_t s) override {
     Level& L0 = lv_[0];
     launch_gather<double, T>(L0.n, r, L0.perm, L0.b, s);
-    vcycle(0, s, false);
+    cycle(0, s, false);
     launch_scatter_cast<T, double>(L0.n, L0.x, L0.perm, e, s);
   }
 
@@ -836,7 +843,7 @@ class Precond final : public PrecondBase {
   // its first colour is then fused into the kernel that writes the level's b.
   ZeroStart<T> zero_start(int l) const {
     ZeroStart<T> zs;
-    if (!pgs_no_ && l < tail_ && pre_ > 0 && lv_[l].coff.size() > 1) {
+    if (!pgs_no_ && !ua_ && l < tail_ && pre_ > 0 && lv_[l].coff.size() > 1) {
       const Level& L = lv_[l];
       zs.n_first = L.coff[1];
       zs.diag = L.diag;
@@ -866,6 +873,130 @@ class Precond final : public PrecondBase {
       if (timer) timer->begin(kind, s);
       launch_gs_colour<T>(A, L.diag, L.coff[c], L.coff[c + 1], L.b, L.x, S[cur], S[cur ^ 1], zero, s);
       if (timer) timer->end(kind, s, L.colour_bytes[c]);
+    }
+  }
+
+  void cycle(int l, hipStream_t s, bool first_done) {
+    if (ua_)
+      kcycle(l, s);
+    else
+      vcycle(l, s, first_done);
+  }
+
+  // The coarsest level of the aggregation AMG: x = A_L^{-1} b.
+  void coarse_solve(hipStream_t s) {
+    Level& L = lv_.back();
+    if (timer) timer->begin(CPR_KSTAT_TAIL, s);
+    launch_dense_gemv<T>(L.n, cinv_, L.b, L.x, s);
+    if (timer) timer->end(CPR_KSTAT_TAIL, s, 8.0 * L.n * L.n + 2.0 * sizeof(T) * L.n);
+  }
+
+  // Nonlinear AMLI-cycle on level l from x = 0, right-hand side lv_[l].b,
+  // result in lv_[l].x: pre-smoothing, residual, restriction, the coarse
+  // correction (the inverse on the coarsest level, else inner_ flexible GCR
+  // steps preconditioned by the next level's cycle), prolongation,
+  // post-smoothing.
+  void kcycle(int l, hipStream_t s) {
+    const int nl = static_cast<int>(lv_.size());
+    if (l == nl - 1) {
+      coarse_solve(s);
+      return;
+    }
+    Level& L = lv_[l];
+    const double sv = sizeof(T);
+    int cur = 0;
+    if (pre_ == 0) launch_fill<T>(L.n, (T)0, L.x, s);
+    for (int w = 0; w < pre_; ++w) {
+      sweep(l, cur, w == 0, s);
+      cur ^= 1;
+    }
+    Level& C = lv_[l + 1];
+    const int kind = l == 0 ? CPR_KSTAT_TRANSFER_L0 : CPR_KSTAT_TRANSFER_COARSE;
+    if (timer) timer->begin(kind, s);
+    launch_csr_residual<T>(L.A.view(), L.b, L.x, L.r, s);
+    if (timer) timer->end(kind, s, L.nnz * (sv + 4) + 4.0 * L.n + 3.0 * L.n * sv);
+    if (timer) timer->begin(kind, s);
+    launch_csr_restrict<T>(L.R.view(), L.r, C.b, ZeroStart<T>{}, s);
+    if (timer) timer->end(kind, s, L.nnz_r * (sv + 4) + 4.0 * C.n + L.n * sv + C.n * sv);
+    if (l + 1 == nl - 1)
+      coarse_solve(s);
+    else
+      gcr(l + 1, s);
+    T* S[2] = {L.s0, L.s1};
+    if (timer) timer->begin(kind, s);
+    launch_prolong_add<T>(L.P.view(), C.x, L.x, S[cur], s);
+    if (timer) timer->end(kind, s, L.nnz_p * (sv + 4) + 4.0 * L.n + C.n * sv + 2.0 * L.n * sv);
+    for (int w = 0; w < post_; ++w) {
+      sweep(l, cur, false, s);
+      cur ^= 1;
+    }
+  }
+
+  // inner_ flexible GCR steps on A_c e = f (f = lv_[c].b on entry, e left in
+  // lv_[c].x), preconditioned by the cycle on level c.
+  void gcr(int c, hipStream_t s) {
+    Level& C = lv_[c];
+    Gcr& g = gcr_[c];
+    const int64_t n = C.n;
+    const MatView<T> A = C.A.view();
+    const int kind = CPR_KSTAT_TRANSFER_COARSE;
+    kcycle(c, s);                                   // z1 = B(f)   (in C.x)
+    launch_csr_spmv<T>(A, C.x, g.w1, s);            // w1 = A z1
+    if (timer) timer->begin(kind, s);
+    launch_gcr_dots<T>(n, g.w1, g.w1, C.b, g.w1, g.part, s);
+    if (inner_ == 1) {
+      launch_gcr_single<T>(n, g.part, C.x, s);      // e = alpha1 z1
+      if (timer) timer->end(kind, s, 4.0 * n * sizeof(T));
+      return;
+    }
+    launch_gcr_step1<T>(n, g.part, C.x, g.z1, C.b, g.w1, g.scal, s);  // z1 kept, f -> r1
+    if (timer) timer->end(kind, s, 7.0 * n * sizeof(T));
+    kcycle(c, s);                                   // z2 = B(r1)  (in C.x)
+    launch_csr_spmv<T>(A, C.x, g.w2, s);            // w2 = A z2
+    if (timer) timer->begin(kind, s);
+    launch_gcr_dots<T>(n, g.w2, g.w1, static_cast<const T*>(nullptr), static_cast<const T*>(nullptr), g.part, s);
+    launch_gcr_orth<T>(n, g.part, g.scal, g.w2, g.w1, C.x, g.z1, C.b, g.part2, s);
+    launch_gcr_finish<T>(n, g.part2, g.scal, C.x, g.z1, s);  // e = alpha1 z1 + alpha2 z2
+    if (timer) timer->end(kind, s, 13.0 * n * sizeof(T));
+  }
+
+  // The aggregation AMG's SETUP on the device: the explicit inverse of the
+  // coarsest matrix (uploaded dense in lu_) by Gauss-Jordan elimination with
+  // partial pivoting, and the GCR vectors of every level that gets a coarse
+  // correction by GCR.
+  void build_amli(hipStream_t s) {
+    const int nl = static_cast<int>(lv_.size());
+    const int n = nL_;
+    double* m = ar_.alloc<double>(n);
+    int32_t* piv = ar_.alloc<int32_t>(n);
+    int32_t* bad = ar_.alloc<int32_t>(1);
+    launch_fill<int32_t>(1, 0, bad, s);
+    for (int k = 0; k < n; ++k) launch_gj_step(n, k, lu_, piv, m, bad, s);
+    std::vector<int32_t> hpiv(n);
+    int32_t hbad = 0;
+    HIPCHK(hipMemcpyAsync(hpiv.data(), piv, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hbad) throw Error(CPR_ERR_SINGULAR_COARSE, "coarsest matrix is singular");
+    // undo the row interchanges as column interchanges, in reverse order
+    std::vector<int32_t> cols(n);
+    std::iota(cols.begin(), cols.end(), 0);
+    for (int k = n - 1; k >= 0; --k) std::swap(cols[k], cols[hpiv[k]]);
+    int32_t* dcols = ar_.upload(cols);
+    cinv_ = ar_.alloc<double>(static_cast<int64_t>(n) * n);
+    launch_permute_cols(n, lu_, dcols, cinv_, s);
+    HIPCHK(hipStreamSynchronize(s));
+    gcr_.resize(nl);
+    for (int c = 1; c + 1 < nl; ++c) {
+      Gcr& g = gcr_[c];
+      const int64_t nc = lv_[c].n;
+      g.z1 = ar_.alloc<T>(nc);
+      g.w1 = ar_.alloc<T>(nc);
+      g.w2 = ar_.alloc<T>(nc);
+      const int G = amli_dot_grid(nc);
+      g.part = ar_.alloc<double>(2 * G);
+      g.part2 = ar_.alloc<double>(2 * G);
+      g.scal = ar_.alloc<double>(4);
     }
   }
 
@@ -941,6 +1072,15 @@ class Precond final : public PrecondBase {
   // PGS-NO smoother (natural order, chunked Gauss-Seidel)
   bool pgs_no_ = false;
   int32_t chunks_ = 1;
+  // aggregation AMG with the nonlinear AMLI-cycle
+  struct Gcr {
+    T *z1 = nullptr, *w1 = nullptr, *w2 = nullptr;
+    double *part = nullptr, *part2 = nullptr, *scal = nullptr;
+  };
+  bool ua_ = false;
+  int inner_ = 2;
+  double* cinv_ = nullptr;
+  std::vector<Gcr> gcr_;
 };
 
 std::unique_ptr<PrecondBase> make_precond(bool fp32, const cpr_params& prm, int32_t n_b,

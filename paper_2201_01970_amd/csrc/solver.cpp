@@ -278,21 +278,29 @@ void cpr_handle::build_precond() {
     // colouring of this level (eq. (strong-matrix) pattern) on its own thread
     level_tasks.push_back(
         std::async(std::launch::async, [Sc = pattern_from_mask(L.A, L.mask, 2)]() { return colour_level(Sc); }));
-    const Pattern S = pattern_from_mask(L.A, L.mask, 1);
-    const Pattern ST = transpose_pattern(S);
-    rs_split(S, ST, L.cf);
-    t_split += now_ms() - tp;
     int32_t nc = 0;
-    for (int8_t c : L.cf) nc += (c == 1);
+    if (prm.amg_kind == 1) {
+      // unsmoothed aggregation: npair passes of pairwise matching, P of 0/1
+      nc = npair_aggregates(L.A, prm.pair_beta, prm.npair, L.agg);
+    } else {
+      const Pattern S = pattern_from_mask(L.A, L.mask, 1);
+      const Pattern ST = transpose_pattern(S);
+      rs_split(S, ST, L.cf);
+      for (int8_t c : L.cf) nc += (c == 1);
+    }
+    t_split += now_ms() - tp;
     if (nc == 0 || static_cast<double>(nc) > 0.9 * n) {
       // coarsening stalled: this level becomes the coarsest and is not smoothed
       level_tasks.pop_back();
       L.cf.clear();
+      L.agg.clear();
       hl.push_back(std::move(L));
       break;
     }
     tp = now_ms();
-    if (!rs_interpolation(L.A, L.mask, 1, L.cf, L.P))
+    if (prm.amg_kind == 1)
+      L.P = aggregation_matrix(L.agg, nc);
+    else if (!rs_interpolation(L.A, L.mask, 1, L.cf, L.P))
       throw Error(CPR_ERR_SINGULAR_COARSE, "zero interpolation denominator");
     t_interp += now_ms() - tp;
     tp = now_ms();
@@ -329,15 +337,18 @@ void cpr_handle::build_precond() {
       std::iota(L.perm.begin(), L.perm.end(), 0);
     }
   }
-  // coarsest dense LU (FP64)
+  // coarsest level, dense (FP64): LU-factored here for the V-cycle; for the
+  // aggregation AMG left unfactored (its inverse is formed on the device)
   const HostCsr& Ac = hl.back().A;
   const int32_t nc = Ac.n_rows;
-  if (nc > 8192) throw Error(CPR_ERR_INVALID_ARG, "coarsening stalled above 8192 rows");
+  if (nc > (prm.amg_kind == 1 ? 16384 : 8192))
+    throw Error(CPR_ERR_INVALID_ARG, "the coarsest level has " + std::to_string(nc) + " rows (coarsening stalled)");
   std::vector<double> lu(static_cast<size_t>(nc) * nc, 0.0);
   for (int32_t i = 0; i < nc; ++i)
     for (int32_t q = Ac.ptr[i]; q < Ac.ptr[i + 1]; ++q) lu[static_cast<size_t>(i) * nc + Ac.col[q]] += Ac.val[q];
   std::vector<int32_t> piv;
-  if (!dense_lu(nc, lu, piv)) throw Error(CPR_ERR_SINGULAR_COARSE, "coarsest matrix is singular");
+  if (prm.amg_kind == 0 && !dense_lu(nc, lu, piv))
+    throw Error(CPR_ERR_SINGULAR_COARSE, "coarsest matrix is singular");
 
   // stage-2 block colouring or factorisation (computed on its own thread since the start)
   Colouring bc = block_task.get();

@@ -94,6 +94,7 @@ struct HostLevel {
   std::vector<int32_t> colour;
   int32_t n_colours = 0;
   std::vector<int8_t> cf;
+  std::vector<int32_t> agg;  // aggregation AMG: aggregate of every row
   HostCsr P;
   std::vector<int32_t> perm;  // device row p -> level row perm[p]
   std::vector<int32_t> coff;  // colour offsets in device order

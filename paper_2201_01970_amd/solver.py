@@ -35,6 +35,10 @@ class Params:
     decoupling: int = 0     # 0 none, 1 quasi-IMPES, 2 ABF
     smoother: int = 0       # 0 PGS-SCM, 1 PGS-NO
     smoother_chunks: int = 256
+    amg_kind: int = 0       # 0 RS AMG + V-cycle, 1 UA-AMG (pairwise matching) + nonlinear AMLI-cycle
+    amli_inner: int = 2
+    npair: int = 2
+    pair_beta: float = 0.25
 
     def to_c(self) -> A.cpr_params:
         p = A.cpr_params()
@@ -238,6 +242,11 @@ class Solver:
         if not coarsest:
             out.update(rs_strong=rs.astype(bool), color_strong=cs.astype(bool), colour=colour, cf=cf)
         return out
+
+    def level_aggregates(self, level):
+        agg = np.empty(self.level_info(level)["n"], dtype=np.int32)
+        A.check(self._lib.cpr_level_aggregates(self._h, int(level), agg.ctypes.data), self._h)
+        return agg
 
     def level_interp(self, level):
         info = self.level_info(level)

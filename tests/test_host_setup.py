@@ -205,3 +205,46 @@ def test_host_bilu0_reports_singular_pivot():
     st = _capi.lib().cpr_host_bilu0(n, rp.ctypes.data, col.ctypes.data, flat.ctypes.data,
                                     *[o.ctypes.data for o in out])
     assert st == _capi.CPR_ERR_SINGULAR_BLOCK
+
+
+def _host_aggregates(A, beta=0.25, npair=2):
+    from paper_2201_01970_amd import _capi
+
+    n = A.n_rows
+    ptr, col, val = (np.ascontiguousarray(A.indptr, dtype=np.int32), np.ascontiguousarray(A.indices, dtype=np.int32),
+                     np.ascontiguousarray(A.data, dtype=np.float64))
+    agg = np.empty(n, dtype=np.int32)
+    na = np.zeros(1, dtype=np.int32)
+    st = _capi.lib().cpr_host_aggregates(n, ptr.ctypes.data, col.ctypes.data, val.ctypes.data, beta, npair,
+                                         agg.ctypes.data, na.ctypes.data)
+    assert st == 0
+    return agg, int(na[0])
+
+
+@pytest.mark.parametrize("npair", [1, 2])
+@pytest.mark.parametrize("which", ["spe10", "channels", "decoupled", "random"])
+def test_host_aggregates_match_oracle(which, npair):
+    """The library's pairwise matching gives exactly the oracle's aggregates
+    (same pairs, same numbering), on pressure matrices of the generated
+    workloads, a quasi-IMPES-decoupled one (non-symmetric, positive entries)
+    and random non-symmetric matrices, for one and two passes."""
+    from oracle import cpr as ocpr
+    from oracle import uaamg
+    from oracle.sparse import csr_from_dense
+
+    if which == "spe10":
+        A = pressure_matrix(Bsr.from_case(bo.case_spe10_like(seed=91, shape=(14, 12, 6))))
+    elif which == "channels":
+        A = pressure_matrix(Bsr.from_case(bo.case_channels(seed=92, shape=(16, 16, 6))))
+    elif which == "decoupled":
+        B = Bsr.from_case(bo.case_small(seed=93, shape=(10, 9, 4)))
+        A = pressure_matrix(ocpr.left_blocks(ocpr.decoupling_weights(B, "quasi-impes"), B))
+    else:
+        rng = np.random.default_rng(94)
+        d = rng.standard_normal((60, 60)) * (rng.random((60, 60)) < 0.1)
+        np.fill_diagonal(d, 5.0)
+        A = csr_from_dense(d)
+    want, nw = uaamg.npair_aggregates(A, 0.25, npair)
+    got, ng = _host_aggregates(A, 0.25, npair)
+    assert ng == nw
+    assert np.array_equal(got, want)
