@@ -50,18 +50,6 @@ struct MatView {
   const T* val = nullptr;
 };
 
-// Kernel timing of the profiler: while `stop` is set on the calling thread,
-// launches go through hipExtLaunchKernelGGL, which has the GPU stamp the
-// start of the first kernel into `start` and the end of each kernel into
-// `stop` (kernel execution only, without the launch latency an event pair
-// recorded around the launch would include).
-struct ExtTiming {
-  hipEvent_t start = nullptr;
-  hipEvent_t stop = nullptr;
-  bool used = false;
-};
-ExtTiming& ext_timing();
-
 // Kernel classes whose launches can be timed with HIP events.
 struct LaunchTimer {
   virtual ~LaunchTimer() = default;

@@ -173,10 +173,10 @@ void launch_gs_grp(const MatView<T>& A, const T* diag, int32_t lo, int32_t hi, c
                    T* s_out, bool zero_start, hipStream_t s) {
   const int grid = div_up((int64_t)(hi - lo) * G, kBlock);
   if (zero_start)
-    CPR_LAUNCH((k_gs_grp<T, G, CH, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag,
+    hipLaunchKernelGGL((k_gs_grp<T, G, CH, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag,
                        b, x, s_in, s_out);
   else
-    CPR_LAUNCH((k_gs_grp<T, G, CH, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag,
+    hipLaunchKernelGGL((k_gs_grp<T, G, CH, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag,
                        b, x, s_in, s_out);
 }
 
@@ -231,10 +231,10 @@ void launch_gs_v16(const MatView<T>& A, const T* diag, int32_t lo, int32_t hi, c
                    T* s_out, bool zero_start, hipStream_t s) {
   const int grid = div_up((int64_t)(hi - lo) * 16, kV16Block);
   if (zero_start)
-    CPR_LAUNCH((k_gs_v16<T, CH, true>), dim3(grid), dim3(kV16Block), 0, s, lo, hi, A.ptr, A.col, A.val, diag,
+    hipLaunchKernelGGL((k_gs_v16<T, CH, true>), dim3(grid), dim3(kV16Block), 0, s, lo, hi, A.ptr, A.col, A.val, diag,
                        b, x, s_in, s_out);
   else
-    CPR_LAUNCH((k_gs_v16<T, CH, false>), dim3(grid), dim3(kV16Block), 0, s, lo, hi, A.ptr, A.col, A.val,
+    hipLaunchKernelGGL((k_gs_v16<T, CH, false>), dim3(grid), dim3(kV16Block), 0, s, lo, hi, A.ptr, A.col, A.val,
                        diag, b, x, s_in, s_out);
 }
 
@@ -243,10 +243,10 @@ void launch_gs_q4(const MatView<T>& A, const T* diag, int32_t lo, int32_t hi, co
                   T* s_out, bool zero_start, hipStream_t s) {
   const int grid = div_up((int64_t)(hi - lo) * 4, kBlock);
   if (zero_start)
-    CPR_LAUNCH((k_gs_q4<T, CH, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag, b,
+    hipLaunchKernelGGL((k_gs_q4<T, CH, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag, b,
                        x, s_in, s_out);
   else
-    CPR_LAUNCH((k_gs_q4<T, CH, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag, b,
+    hipLaunchKernelGGL((k_gs_q4<T, CH, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.ptr, A.col, A.val, diag, b,
                        x, s_in, s_out);
 }
 
@@ -256,10 +256,10 @@ void launch_gs_sell(const MatView<T>& A, const T* diag, int32_t lo, int32_t hi, 
   const int32_t base = lo & ~63;
   const int grid = div_up(hi - base, kBlock);
   if (zero_start)
-    CPR_LAUNCH((k_gs_sell<T, U, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.width, A.ptr, A.col, A.val,
+    hipLaunchKernelGGL((k_gs_sell<T, U, true>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.width, A.ptr, A.col, A.val,
                        diag, b, x, s_in, s_out);
   else
-    CPR_LAUNCH((k_gs_sell<T, U, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.width, A.ptr, A.col,
+    hipLaunchKernelGGL((k_gs_sell<T, U, false>), dim3(grid), dim3(kBlock), 0, s, lo, hi, A.width, A.ptr, A.col,
                        A.val, diag, b, x, s_in, s_out);
 }
 
@@ -345,7 +345,7 @@ void launch_gs_chunks(const MatView<T>& A, const T* diag, int32_t n_chunks, cons
   if (n == 0) return;
   const int32_t nch = n_chunks < 1 ? 1 : (n_chunks > n ? n : n_chunks);
   const int32_t q = n / nch, r = n % nch;
-  CPR_LAUNCH((k_gs_chunks<T>), dim3(div_up(nch, 64)), dim3(64), 0, s, nch, q, r, A.ptr, A.col, A.val, diag, b,
+  hipLaunchKernelGGL((k_gs_chunks<T>), dim3(div_up(nch, 64)), dim3(64), 0, s, nch, q, r, A.ptr, A.col, A.val, diag, b,
                      x, snap);
   CPR_LAUNCH_CHECK();
 }
@@ -463,28 +463,28 @@ __global__ __launch_bounds__(kBlock) void k_rows_v16(int32_t n, const int32_t* _
 template <typename T, int CH, int MODE>
 void launch_rows_v16(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, const ZeroStart<T>& zs,
                      hipStream_t s) {
-  CPR_LAUNCH((k_rows_v16<T, CH, MODE>), dim3(div_up((int64_t)A.n_rows * 16, kBlock)), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL((k_rows_v16<T, CH, MODE>), dim3(div_up((int64_t)A.n_rows * 16, kBlock)), dim3(kBlock), 0, s,
                      A.n_rows, A.ptr, A.col, A.val, b, x, y, snap, zs);
 }
 
 template <typename T, int CH, int MODE>
 void launch_rows_q4(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, const ZeroStart<T>& zs,
                     hipStream_t s) {
-  CPR_LAUNCH((k_rows_q4<T, CH, MODE>), dim3(div_up((int64_t)A.n_rows * 4, kBlock)), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL((k_rows_q4<T, CH, MODE>), dim3(div_up((int64_t)A.n_rows * 4, kBlock)), dim3(kBlock), 0, s,
                      A.n_rows, A.ptr, A.col, A.val, b, x, y, snap, zs);
 }
 
 template <typename T, int G, int CH, int MODE>
 void launch_rows_grp(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, const ZeroStart<T>& zs,
                      hipStream_t s) {
-  CPR_LAUNCH((k_rows_grp<T, G, CH, MODE>), dim3(div_up((int64_t)A.n_rows * G, kBlock)), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL((k_rows_grp<T, G, CH, MODE>), dim3(div_up((int64_t)A.n_rows * G, kBlock)), dim3(kBlock), 0, s,
                      A.n_rows, A.ptr, A.col, A.val, b, x, y, snap, zs);
 }
 
 template <typename T, int U, int MODE>
 void launch_rows_sell(const MatView<T>& A, const T* b, const T* x, T* y, T* snap, const ZeroStart<T>& zs,
                       hipStream_t s) {
-  CPR_LAUNCH((k_rows_sell<T, U, MODE>), dim3(div_up(A.n_rows, kBlock)), dim3(kBlock), 0, s, A.n_rows, A.width,
+  hipLaunchKernelGGL((k_rows_sell<T, U, MODE>), dim3(div_up(A.n_rows, kBlock)), dim3(kBlock), 0, s, A.n_rows, A.width,
                      A.ptr, A.col, A.val, b, x, y, snap, zs);
 }
 

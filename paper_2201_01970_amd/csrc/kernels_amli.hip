@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_gcr_finish(int64_t n, const double* 
 
 template <typename T>
 void launch_gcr_dots(int64_t n, const T* x1, const T* y1, const T* x2, const T* y2, double* part, hipStream_t s) {
-  CPR_LAUNCH((k_dot2<T>), dim3(dot_grid(n)), dim3(kBlock), 0, s, n, x1, y1, x2, y2, part);
+  hipLaunchKernelGGL((k_dot2<T>), dim3(dot_grid(n)), dim3(kBlock), 0, s, n, x1, y1, x2, y2, part);
   CPR_LAUNCH_CHECK();
 }
 
@@ -164,14 +164,14 @@ template <typename T>
 void launch_gcr_step1(int64_t n, const double* part, const T* x, T* z1, T* f, const T* w1, double* scal,
                       hipStream_t s) {
   const int G = dot_grid(n);
-  CPR_LAUNCH((k_gcr_step1<T>), dim3(G), dim3(kBlock), 0, s, n, part, G, x, z1, f, w1, scal);
+  hipLaunchKernelGGL((k_gcr_step1<T>), dim3(G), dim3(kBlock), 0, s, n, part, G, x, z1, f, w1, scal);
   CPR_LAUNCH_CHECK();
 }
 
 template <typename T>
 void launch_gcr_single(int64_t n, const double* part, T* x, hipStream_t s) {
   const int G = dot_grid(n);
-  CPR_LAUNCH((k_gcr_single<T>), dim3(G), dim3(kBlock), 0, s, n, part, G, x);
+  hipLaunchKernelGGL((k_gcr_single<T>), dim3(G), dim3(kBlock), 0, s, n, part, G, x);
   CPR_LAUNCH_CHECK();
 }
 
@@ -179,14 +179,14 @@ template <typename T>
 void launch_gcr_orth(int64_t n, const double* part, const double* scal, T* w2, const T* w1, T* x, const T* z1,
                      const T* r1, double* part2, hipStream_t s) {
   const int G = dot_grid(n);
-  CPR_LAUNCH((k_gcr_orth<T>), dim3(G), dim3(kBlock), 0, s, n, part, G, scal, w2, w1, x, z1, r1, part2);
+  hipLaunchKernelGGL((k_gcr_orth<T>), dim3(G), dim3(kBlock), 0, s, n, part, G, scal, w2, w1, x, z1, r1, part2);
   CPR_LAUNCH_CHECK();
 }
 
 template <typename T>
 void launch_gcr_finish(int64_t n, const double* part2, const double* scal, T* x, const T* z1, hipStream_t s) {
   const int G = dot_grid(n);
-  CPR_LAUNCH((k_gcr_finish<T>), dim3(G), dim3(kBlock), 0, s, n, part2, G, scal, x, z1);
+  hipLaunchKernelGGL((k_gcr_finish<T>), dim3(G), dim3(kBlock), 0, s, n, part2, G, scal, x, z1);
   CPR_LAUNCH_CHECK();
 }
 
@@ -281,14 +281,14 @@ __global__ __launch_bounds__(kBlock) void k_permute_cols(int n, const double* __
 }
 
 void launch_gj_step(int n, int k, double* a, int32_t* piv, double* m, int32_t* bad, hipStream_t s) {
-  CPR_LAUNCH(k_gj_pivot, dim3(1), dim3(kGjBlock), 0, s, n, k, a, piv, m, bad);
+  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kGjBlock), 0, s, n, k, a, piv, m, bad);
   CPR_LAUNCH_CHECK();
-  CPR_LAUNCH(k_gj_eliminate, dim3(n), dim3(kBlock), 0, s, n, k, a, m);
+  hipLaunchKernelGGL(k_gj_eliminate, dim3(n), dim3(kBlock), 0, s, n, k, a, m);
   CPR_LAUNCH_CHECK();
 }
 
 void launch_permute_cols(int n, const double* src, const int32_t* cols, double* dst, hipStream_t s) {
-  CPR_LAUNCH(k_permute_cols, dim3(n), dim3(kBlock), 0, s, n, src, cols, dst);
+  hipLaunchKernelGGL(k_permute_cols, dim3(n), dim3(kBlock), 0, s, n, src, cols, dst);
   CPR_LAUNCH_CHECK();
 }
 
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_gemv(int n, const double* __re
 template <typename T>
 void launch_dense_gemv(int n, const double* ainv, const T* b, T* x, hipStream_t s) {
   if (n == 0) return;
-  CPR_LAUNCH((k_dense_gemv<T>), dim3(div_up(n, kBlock / 64)), dim3(kBlock), 0, s, n, ainv, b, x);
+  hipLaunchKernelGGL((k_dense_gemv<T>), dim3(div_up(n, kBlock / 64)), dim3(kBlock), 0, s, n, ainv, b, x);
   CPR_LAUNCH_CHECK();
 }
 template void launch_dense_gemv<double>(int, const double*, const double*, double*, hipStream_t);

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_bilu_backward(int32_t lo, int32_t hi
 template <typename T>
 void launch_bilu_residual(const SellView<T>& R, const double* v, const T* pe, T* r, hipStream_t s) {
   if (R.n_rows == 0) return;
-  CPR_LAUNCH((k_bilu_residual<T>), dim3(div_up(R.n_rows, kBlock)), dim3(kBlock), 0, s, R.n_rows,
+  hipLaunchKernelGGL((k_bilu_residual<T>), dim3(div_up(R.n_rows, kBlock)), dim3(kBlock), 0, s, R.n_rows,
                      R.slice_ptr, R.col, R.val, v, pe, r);
   CPR_LAUNCH_CHECK();
 }
@@ -149,7 +149,7 @@ void launch_bilu_forward(int32_t lo, int32_t hi, const SellView<T>& L, const int
                          hipStream_t s) {
   if (hi <= lo) return;
   const int32_t base = lo & ~63;
-  CPR_LAUNCH((k_bilu_forward<T>), dim3(div_up(hi - base, kBlock)), dim3(kBlock), 0, s, lo, hi, L.slice_ptr,
+  hipLaunchKernelGGL((k_bilu_forward<T>), dim3(div_up(hi - base, kBlock)), dim3(kBlock), 0, s, lo, hi, L.slice_ptr,
                      L.col, L.val, row, r, y);
   CPR_LAUNCH_CHECK();
 }
@@ -159,7 +159,7 @@ void launch_bilu_backward(int32_t lo, int32_t hi, const SellView<T>& U, const T*
                           const T* y, const T* pe, T* d, T* z, hipStream_t s) {
   if (hi <= lo) return;
   const int32_t base = lo & ~63;
-  CPR_LAUNCH((k_bilu_backward<T>), dim3(div_up(hi - base, kBlock)), dim3(kBlock), 0, s, lo, hi, U.slice_ptr,
+  hipLaunchKernelGGL((k_bilu_backward<T>), dim3(div_up(hi - base, kBlock)), dim3(kBlock), 0, s, lo, hi, U.slice_ptr,
                      U.col, U.val, uinv, ld, row, y, pe, d, z);
   CPR_LAUNCH_CHECK();
 }

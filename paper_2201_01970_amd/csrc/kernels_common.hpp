@@ -1,7 +1,6 @@
 // Helpers shared by the HIP kernel files (device side only).
 #pragma once
 
-#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -9,21 +8,6 @@
 #include "device.hpp"
 
 namespace cpr {
-
-// Every kernel launch: through hipExtLaunchKernelGGL with the profiler's
-// events while a timed class is open on this thread (see ExtTiming), else a
-// plain launch.
-#define CPR_LAUNCH(KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                                            \
-  do {                                                                                                \
-    ::cpr::ExtTiming& cpr_t_ = ::cpr::ext_timing();                                                   \
-    if (cpr_t_.stop) {                                                                                \
-      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, cpr_t_.start, cpr_t_.stop, 0, __VA_ARGS__); \
-      cpr_t_.start = nullptr;                                                                         \
-      cpr_t_.used = true;                                                                             \
-    } else {                                                                                          \
-      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                            \
-    }                                                                                                 \
-  } while (0)
 
 // The hardware hands workgroup b of a launch to XCD (b mod 8).  Renumbering the
 // workgroups so that each XCD receives one contiguous range of the logical

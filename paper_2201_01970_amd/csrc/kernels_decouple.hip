@@ -90,17 +90,17 @@ __global__ __launch_bounds__(kBlock) void k_block_gemv(int32_t n, const T* __res
 void launch_decouple(int32_t n, const int32_t* rp, const int32_t* col, const double* vals, int32_t kind, double* w,
                      double* wa, int32_t* bad_row, hipStream_t s) {
   if (n == 0) return;
-  CPR_LAUNCH(k_decouple_weights, dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, rp, col, vals, kind, w,
+  hipLaunchKernelGGL(k_decouple_weights, dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, rp, col, vals, kind, w,
                      bad_row);
   CPR_LAUNCH_CHECK();
-  CPR_LAUNCH(k_left_blocks, dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, rp, w, vals, wa);
+  hipLaunchKernelGGL(k_left_blocks, dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, rp, w, vals, wa);
   CPR_LAUNCH_CHECK();
 }
 
 template <typename T>
 void launch_block_gemv(int32_t n, const T* w, const double* v, double* out, hipStream_t s) {
   if (n == 0) return;
-  CPR_LAUNCH((k_block_gemv<T>), dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, w, v, out);
+  hipLaunchKernelGGL((k_block_gemv<T>), dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, w, v, out);
   CPR_LAUNCH_CHECK();
 }
 template void launch_block_gemv<double>(int32_t, const double*, const double*, double*, hipStream_t);

@@ -72,10 +72,10 @@ void launch_bsr_spmv(const SellView<TA>& A, const TX* x, const double* b, double
   if (A.n_rows == 0) return;
   const int grid = div_up(A.n_rows, kBlock);
   if (b)
-    CPR_LAUNCH((k_bsr_spmv<TA, TX, true>), dim3(grid), dim3(kBlock), 0, s, A.n_rows, A.slice_ptr, A.col,
+    hipLaunchKernelGGL((k_bsr_spmv<TA, TX, true>), dim3(grid), dim3(kBlock), 0, s, A.n_rows, A.slice_ptr, A.col,
                        A.val, x, b, y);
   else
-    CPR_LAUNCH((k_bsr_spmv<TA, TX, false>), dim3(grid), dim3(kBlock), 0, s, A.n_rows, A.slice_ptr, A.col,
+    hipLaunchKernelGGL((k_bsr_spmv<TA, TX, false>), dim3(grid), dim3(kBlock), 0, s, A.n_rows, A.slice_ptr, A.col,
                        A.val, x, b, y);
   CPR_LAUNCH_CHECK();
 }
@@ -105,7 +105,7 @@ template <typename T>
 void launch_restrict_pressure(int32_t n, const double* v, const int32_t* perm, T* rp, const ZeroStart<T>& zs,
                               hipStream_t s) {
   if (n == 0) return;
-  CPR_LAUNCH((k_restrict_pressure<T>), dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, v, perm, rp, zs);
+  hipLaunchKernelGGL((k_restrict_pressure<T>), dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, v, perm, rp, zs);
   CPR_LAUNCH_CHECK();
 }
 template void launch_restrict_pressure<double>(int32_t, const double*, const int32_t*, double*,
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int32_t n, const T* __restri
 template <typename T>
 void launch_scatter(int32_t n, const T* e, const int32_t* perm, T* pe, hipStream_t s) {
   if (n == 0) return;
-  CPR_LAUNCH((k_scatter<T>), dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, e, perm, pe);
+  hipLaunchKernelGGL((k_scatter<T>), dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, e, perm, pe);
   CPR_LAUNCH_CHECK();
 }
 template void launch_scatter<double>(int32_t, const double*, const int32_t*, double*, hipStream_t);
@@ -202,7 +202,7 @@ void launch_stage2(const SellView<T>& A, int32_t lo, int32_t hi, const int32_t* 
                    int32_t dinv_ld, const double* v, const T* pe, T* z, hipStream_t s) {
   if (hi <= lo) return;
   const int32_t base = lo & ~63;
-  CPR_LAUNCH((k_stage2<T>), dim3(div_up(hi - base, kBlock)), dim3(kBlock), 0, s, lo, hi, A.slice_ptr,
+  hipLaunchKernelGGL((k_stage2<T>), dim3(div_up(hi - base, kBlock)), dim3(kBlock), 0, s, lo, hi, A.slice_ptr,
                      A.col, A.val, cell, dinv, dinv_ld, v, pe, z);
   CPR_LAUNCH_CHECK();
 }
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_setup_values(int32_t n, const int32_
 void launch_setup_values(int32_t n, const int32_t* rp, const int32_t* col, const double* vals, double* pval,
                          uint8_t* nonzero, int32_t* bad_row, hipStream_t s) {
   if (n == 0) return;
-  CPR_LAUNCH(k_setup_values, dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, rp, col, vals, pval, nonzero,
+  hipLaunchKernelGGL(k_setup_values, dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, rp, col, vals, pval, nonzero,
                      bad_row);
   CPR_LAUNCH_CHECK();
 }
@@ -285,7 +285,7 @@ template <typename T>
 void launch_block_inverse(int32_t n, const double* vals, const int64_t* diag_pos, T* dinv, int32_t ld,
                           int32_t* singular, hipStream_t s) {
   if (n == 0) return;
-  CPR_LAUNCH((k_block_inverse<T>), dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, vals, diag_pos, dinv, ld,
+  hipLaunchKernelGGL((k_block_inverse<T>), dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, vals, diag_pos, dinv, ld,
                      singular);
   CPR_LAUNCH_CHECK();
 }
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_bsr_values_to_sell(int64_t nnzb, con
 template <typename T>
 void launch_bsr_values_to_sell(int64_t nnzb, const double* vals, const int64_t* pos, T* sv, hipStream_t s) {
   if (nnzb == 0) return;
-  CPR_LAUNCH((k_bsr_values_to_sell<T>), dim3(div_up(nnzb, kBlock)), dim3(kBlock), 0, s, nnzb, vals, pos, sv);
+  hipLaunchKernelGGL((k_bsr_values_to_sell<T>), dim3(div_up(nnzb, kBlock)), dim3(kBlock), 0, s, nnzb, vals, pos, sv);
   CPR_LAUNCH_CHECK();
 }
 template void launch_bsr_values_to_sell<double>(int64_t, const double*, const int64_t*, double*, hipStream_t);
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_strength(int32_t n, const int32_t* _
 void launch_strength(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, double theta_rs,
                      double theta_color, uint8_t* mask, hipStream_t s) {
   if (n == 0) return;
-  CPR_LAUNCH(k_strength, dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, ptr, col, val, theta_rs,
+  hipLaunchKernelGGL(k_strength, dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, ptr, col, val, theta_rs,
                      theta_color, mask);
   CPR_LAUNCH_CHECK();
 }
@@ -371,13 +371,13 @@ __global__ __launch_bounds__(kBlock) void k_scatter_cast(int32_t n, const TS* __
 template <typename TS, typename TD>
 void launch_gather(int32_t n, const TS* src, const int32_t* perm, TD* dst, hipStream_t s) {
   if (n == 0) return;
-  CPR_LAUNCH((k_gather<TS, TD>), dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, src, perm, dst);
+  hipLaunchKernelGGL((k_gather<TS, TD>), dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, src, perm, dst);
   CPR_LAUNCH_CHECK();
 }
 template <typename TS, typename TD>
 void launch_scatter_cast(int32_t n, const TS* src, const int32_t* perm, TD* dst, hipStream_t s) {
   if (n == 0) return;
-  CPR_LAUNCH((k_scatter_cast<TS, TD>), dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, src, perm, dst);
+  hipLaunchKernelGGL((k_scatter_cast<TS, TD>), dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, src, perm, dst);
   CPR_LAUNCH_CHECK();
 }
 #define CPR_INST_GS(TS, TD)                                                                   \
@@ -398,7 +398,7 @@ template <typename T>
 void launch_fill(int64_t n, T value, T* dst, hipStream_t s) {
   if (n == 0) return;
   const int grid = (int)std::min<int64_t>(div_up(n, kBlock), 4096);
-  CPR_LAUNCH((k_fill<T>), dim3(grid), dim3(kBlock), 0, s, n, value, dst);
+  hipLaunchKernelGGL((k_fill<T>), dim3(grid), dim3(kBlock), 0, s, n, value, dst);
   CPR_LAUNCH_CHECK();
 }
 template void launch_fill<double>(int64_t, double, double*, hipStream_t);
@@ -414,7 +414,7 @@ template <typename TS, typename TD>
 void launch_copy_cast(int64_t n, const TS* src, TD* dst, hipStream_t s) {
   if (n == 0) return;
   const int grid = (int)std::min<int64_t>(div_up(n, kBlock), 8192);
-  CPR_LAUNCH((k_copy_cast<TS, TD>), dim3(grid), dim3(kBlock), 0, s, n, src, dst);
+  hipLaunchKernelGGL((k_copy_cast<TS, TD>), dim3(grid), dim3(kBlock), 0, s, n, src, dst);
   CPR_LAUNCH_CHECK();
 }
 template void launch_copy_cast<double, double>(int64_t, const double*, double*, hipStream_t);
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_int_diff(int64_t n, const int32_t* _
 void launch_int_diff(int64_t n, const int32_t* a, const int32_t* b, int32_t* flag, hipStream_t s) {
   if (n <= 0) return;
   const int grid = (int)std::min<int64_t>(div_up(n, kBlock), 4096);
-  CPR_LAUNCH(k_int_diff, dim3(grid), dim3(kBlock), 0, s, n, a, b, flag);
+  hipLaunchKernelGGL(k_int_diff, dim3(grid), dim3(kBlock), 0, s, n, a, b, flag);
   CPR_LAUNCH_CHECK();
 }
 
@@ -450,11 +450,11 @@ void launch_copy_bytes(int64_t n_bytes, const void* src, void* dst, hipStream_t 
   const int64_t n16 = n_bytes / 16;
   if (n16 > 0) {
     const int grid = (int)std::min<int64_t>(div_up(n16, kBlock), 8192);
-    CPR_LAUNCH(k_copy_bytes, dim3(grid), dim3(kBlock), 0, s, n16, (const uint4*)src, (uint4*)dst);
+    hipLaunchKernelGGL(k_copy_bytes, dim3(grid), dim3(kBlock), 0, s, n16, (const uint4*)src, (uint4*)dst);
   }
   const int64_t tail = n_bytes - 16 * n16;
   if (tail > 0)
-    CPR_LAUNCH(k_copy_tail, dim3(1), dim3(16), 0, s, tail, (const uint8_t*)src + 16 * n16,
+    hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(16), 0, s, tail, (const uint8_t*)src + 16 * n16,
                        (uint8_t*)dst + 16 * n16);
   CPR_LAUNCH_CHECK();
 }

@@ -114,7 +114,7 @@ void launch_multidot(int64_t n, const double* w, const double* V, int64_t ld, in
   for (int c = 0; c < nb; c += kNbMax) {
     const int cnt = std::min(kNbMax, nb - c);
 #define CALL(K)                                                                                      \
-  CPR_LAUNCH((k_multidot<K>), dim3(grid), dim3(kBlock), 0, s, n, w, V, ld, j0 + c, \
+  hipLaunchKernelGGL((k_multidot<K>), dim3(grid), dim3(kBlock), 0, s, n, w, V, ld, j0 + c, \
                      partial + (int64_t)c * grid)
     CPR_NB_SWITCH(cnt, CALL)
 #undef CALL
@@ -130,13 +130,13 @@ void launch_axpy_norm(int64_t n, double* w, const double* V, int64_t ld, int j0,
     const bool last = c + cnt >= nb;
     if (last && norm_partial) {
 #define CALL(K)                                                                                            \
-  CPR_LAUNCH((k_axpy_norm<K, true>), dim3(grid), dim3(kBlock), 0, s, n, w, V, ld, j0 + c, h + c, \
+  hipLaunchKernelGGL((k_axpy_norm<K, true>), dim3(grid), dim3(kBlock), 0, s, n, w, V, ld, j0 + c, h + c, \
                      norm_partial)
       CPR_NB_SWITCH(cnt, CALL)
 #undef CALL
     } else {
 #define CALL(K)                                                                                             \
-  CPR_LAUNCH((k_axpy_norm<K, false>), dim3(grid), dim3(kBlock), 0, s, n, w, V, ld, j0 + c, h + c, \
+  hipLaunchKernelGGL((k_axpy_norm<K, false>), dim3(grid), dim3(kBlock), 0, s, n, w, V, ld, j0 + c, h + c, \
                      norm_partial)
       CPR_NB_SWITCH(cnt, CALL)
 #undef CALL
@@ -150,7 +150,7 @@ void launch_update_x(int64_t n, double* x, const TZ* Z, int64_t ld, int k, const
   const int grid = krylov_grid(n);
   for (int c = 0; c < k; c += kNbMax) {
     const int cnt = std::min(kNbMax, k - c);
-#define CALL(K) CPR_LAUNCH((k_update_x<K, TZ>), dim3(grid), dim3(kBlock), 0, s, n, x, Z, ld, c, y)
+#define CALL(K) hipLaunchKernelGGL((k_update_x<K, TZ>), dim3(grid), dim3(kBlock), 0, s, n, x, Z, ld, c, y)
     CPR_NB_SWITCH(cnt, CALL)
 #undef CALL
   }
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_norm_partial(int64_t n, const double
 }
 
 void launch_norm_partial(int64_t n, const double* v, double* partial, hipStream_t s) {
-  CPR_LAUNCH(k_norm_partial, dim3(krylov_grid(n)), dim3(kBlock), 0, s, n, v, partial);
+  hipLaunchKernelGGL(k_norm_partial, dim3(krylov_grid(n)), dim3(kBlock), 0, s, n, v, partial);
   CPR_LAUNCH_CHECK();
 }
 
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(const double* __rest
 
 void launch_reduce_partials(const double* partial, int grid, int count, double* out, hipStream_t s) {
   if (count == 0) return;
-  CPR_LAUNCH(k_reduce_partials, dim3(count), dim3(kBlock), 0, s, partial, grid, out);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(count), dim3(kBlock), 0, s, partial, grid, out);
   CPR_LAUNCH_CHECK();
 }
 
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_scale_div(int64_t n, const double* _
 }
 
 void launch_scale_div(int64_t n, const double* w, const double* h, double* v, hipStream_t s) {
-  CPR_LAUNCH(k_scale_div, dim3(krylov_grid(n)), dim3(kBlock), 0, s, n, w, h, v);
+  hipLaunchKernelGGL(k_scale_div, dim3(krylov_grid(n)), dim3(kBlock), 0, s, n, w, h, v);
   CPR_LAUNCH_CHECK();
 }
 
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_givens(int m, int j, const double* _
 
 void launch_givens(int m, int j, const double* norm_partial, int grid, double* H, double* cs, double* sn, double* g,
                    double* hnorm, double* report, hipStream_t s) {
-  CPR_LAUNCH(k_givens, dim3(1), dim3(kBlock), 0, s, m, j, norm_partial, grid, H, cs, sn, g, hnorm, report);
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(kBlock), 0, s, m, j, norm_partial, grid, H, cs, sn, g, hnorm, report);
   CPR_LAUNCH_CHECK();
 }
 
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_start_cycle(int m, const double* __r
 
 void launch_start_cycle(int m, const double* norm_partial, int grid, double* g, double* hnorm, double* report,
                         hipStream_t s) {
-  CPR_LAUNCH(k_start_cycle, dim3(1), dim3(kBlock), 0, s, m, norm_partial, grid, g, hnorm, report);
+  hipLaunchKernelGGL(k_start_cycle, dim3(1), dim3(kBlock), 0, s, m, norm_partial, grid, g, hnorm, report);
   CPR_LAUNCH_CHECK();
 }
 
@@ -279,7 +279,7 @@ __global__ void k_backsolve(int m, int k, const double* __restrict__ H, const do
 
 void launch_backsolve(int m, int k, const double* H, const double* g, double* y, hipStream_t s) {
   if (k == 0) return;
-  CPR_LAUNCH(k_backsolve, dim3(1), dim3(64), 0, s, m, k, H, g, y);
+  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, m, k, H, g, y);
   CPR_LAUNCH_CHECK();
 }
 

@@ -265,7 +265,7 @@ size_t tail_lds_limit() {
 template <typename T>
 void launch_tail_vcycle(const TailLevel<T>* levels, int nlev, int pre, int post, int32_t n_coarse, const double* lu,
                         const uint32_t* img, const TailLayout& lay, hipStream_t s) {
-  CPR_LAUNCH((k_tail_vcycle<T>), dim3(1), dim3(kTailThreads), lay.lds_bytes, s, levels, nlev, pre, post,
+  hipLaunchKernelGGL((k_tail_vcycle<T>), dim3(1), dim3(kTailThreads), lay.lds_bytes, s, levels, nlev, pre, post,
                      n_coarse, lu, img, lay);
   CPR_LAUNCH_CHECK();
 }

@@ -26,21 +26,14 @@ void hip_check(hipError_t e, const char* what, const char* file, int line) {
 }
 
 // ------------------------------------------------------------------ profiler
-ExtTiming& ext_timing() {
-  static thread_local ExtTiming t;
-  return t;
-}
-
 Profiler::~Profiler() {
   for (auto& r : pending_) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
   }
   for (hipEvent_t e : free_) (void)hipEventDestroy(e);
-  for (int k = 0; k < CPR_KSTAT_COUNT; ++k) {
-    if (open_a_[k]) (void)hipEventDestroy(open_a_[k]);
-    if (open_b_[k]) (void)hipEventDestroy(open_b_[k]);
-  }
+  for (hipEvent_t e : open_ev_)
+    if (e) (void)hipEventDestroy(e);
 }
 
 void Profiler::enable(bool on) {
@@ -59,35 +52,29 @@ hipEvent_t Profiler::get_event() {
     free_.pop_back();
     return e;
   }
+  // Timing-only events: without the system-scope fence a recorded event
+  // otherwise performs (a cache writeback and invalidation that would both
+  // lengthen the measured interval and slow the next kernel); the profiler
+  // reads them after synchronising the stream.
   hipEvent_t e;
   std::lock_guard<std::mutex> lk(device_api_mutex());
-  HIPCHK(hipEventCreate(&e));
+  HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   return e;
 }
 
-// A class's launches between begin and end are stamped by the GPU itself
-// (start of the first kernel, end of the last; see ExtTiming).
-void Profiler::begin(int kind, hipStream_t) {
+void Profiler::begin(int kind, hipStream_t s) {
   if (!on_) return;
-  open_a_[kind] = get_event();
-  open_b_[kind] = get_event();
-  ExtTiming& t = ext_timing();
-  t.start = open_a_[kind];
-  t.stop = open_b_[kind];
-  t.used = false;
+  hipEvent_t e = get_event();
+  HIPCHK(hipEventRecord(e, s));
+  open_ev_[kind] = e;
 }
 
-void Profiler::end(int kind, hipStream_t, double b) {
-  if (!on_ || !open_a_[kind]) return;
-  ExtTiming& t = ext_timing();
-  if (t.used) {
-    pending_.push_back({kind, open_a_[kind], open_b_[kind], b});
-  } else {  // nothing was launched
-    free_.push_back(open_a_[kind]);
-    free_.push_back(open_b_[kind]);
-  }
-  t = ExtTiming{};
-  open_a_[kind] = open_b_[kind] = nullptr;
+void Profiler::end(int kind, hipStream_t s, double b) {
+  if (!on_ || !open_ev_[kind]) return;
+  hipEvent_t e = get_event();
+  HIPCHK(hipEventRecord(e, s));
+  pending_.push_back({kind, open_ev_[kind], e, b});
+  open_ev_[kind] = nullptr;
 }
 
 void Profiler::collect() {

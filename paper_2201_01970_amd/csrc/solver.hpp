@@ -134,7 +134,7 @@ class Profiler : public LaunchTimer {
   bool on_ = false;
   std::vector<Rec> pending_;
   std::vector<hipEvent_t> free_;
-  hipEvent_t open_a_[CPR_KSTAT_COUNT] = {}, open_b_[CPR_KSTAT_COUNT] = {};
+  hipEvent_t open_ev_[CPR_KSTAT_COUNT] = {};
 };
 
 class PrecondBase {
