@@ -583,9 +583,9 @@ class Precond final : public PrecondBase {
       }
     }
     nL_ = lv_.back().n;
-    lu_ = ar_.upload(lu);
-    if (ua_) build_amli(s);  // coarsest inverse and the GCR buffers; no tail kernel
+    if (ua_) build_amli(lu, s);  // coarsest inverse and the GCR buffers; no tail kernel
     if (!ua_) {
+    lu_ = ar_.upload(lu);
     // compose the factorisation's row swaps: (P b)_i = b[rperm[i]]
     std::vector<int32_t> rperm(piv.size());
     std::iota(rperm.begin(), rperm.end(), 0);
@@ -961,17 +961,19 @@ class Precond final : public PrecondBase {
   }
 
   // The aggregation AMG's SETUP on the device: the explicit inverse of the
-  // coarsest matrix (uploaded dense in lu_) by Gauss-Jordan elimination with
-  // partial pivoting, and the GCR vectors of every level that gets a coarse
-  // correction by GCR.
-  void build_amli(hipStream_t s) {
+  // coarsest matrix (dense, row-major) by Gauss-Jordan elimination with
+  // partial pivoting in SETUP-only memory, and the GCR vectors of every level
+  // that gets a coarse correction by GCR.
+  void build_amli(const std::vector<double>& dense, hipStream_t s) {
     const int nl = static_cast<int>(lv_.size());
     const int n = nL_;
-    double* m = ar_.alloc<double>(n);
-    int32_t* piv = ar_.alloc<int32_t>(n);
-    int32_t* bad = ar_.alloc<int32_t>(1);
+    Arena work;  // released when SETUP returns
+    double* a = work.upload(dense);
+    double* m = work.alloc<double>(n);
+    int32_t* piv = work.alloc<int32_t>(n);
+    int32_t* bad = work.alloc<int32_t>(1);
     launch_fill<int32_t>(1, 0, bad, s);
-    for (int k = 0; k < n; ++k) launch_gj_step(n, k, lu_, piv, m, bad, s);
+    for (int k = 0; k < n; ++k) launch_gj_step(n, k, a, piv, m, bad, s);
     std::vector<int32_t> hpiv(n);
     int32_t hbad = 0;
     HIPCHK(hipMemcpyAsync(hpiv.data(), piv, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -982,9 +984,9 @@ class Precond final : public PrecondBase {
     std::vector<int32_t> cols(n);
     std::iota(cols.begin(), cols.end(), 0);
     for (int k = n - 1; k >= 0; --k) std::swap(cols[k], cols[hpiv[k]]);
-    int32_t* dcols = ar_.upload(cols);
+    int32_t* dcols = work.upload(cols);
     cinv_ = ar_.alloc<double>(static_cast<int64_t>(n) * n);
-    launch_permute_cols(n, lu_, dcols, cinv_, s);
+    launch_permute_cols(n, a, dcols, cinv_, s);
     HIPCHK(hipStreamSynchronize(s));
     gcr_.resize(nl);
     for (int c = 1; c + 1 < nl; ++c) {
