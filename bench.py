@@ -33,9 +33,12 @@ def _pct(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def cpu_baseline(workload, shape_full, gpu_its, n_full):
+def cpu_baseline(workload, shape_full, gpu_its, n_full, coarse_max=50):
     """Time the oracle (single thread) on a scaled-down grid of the same
-    workload and scale up.
+    workload and scale up.  coarse_max: the AMG's coarsest size in the GPU
+    solve; the sample coarsens to the same fraction of its rows (at least 50),
+    so that its hierarchy has about as many levels and the dense coarsest
+    solve about the same share of the work as at full size.
 
     The sample is the workload's own generator on the grid shrunk by 2.5 in
     every direction (24 x 88 x 34, 70K cells, 10 AMG levels, for the
@@ -51,6 +54,7 @@ def cpu_baseline(workload, shape_full, gpu_its, n_full):
 
     import numpy as np
 
+    from oracle import amg as oamg
     from oracle import cpr as ocpr
     from oracle import fgmres as ofg
     from workloads import blackoil as bo
@@ -66,7 +70,8 @@ def cpu_baseline(workload, shape_full, gpu_its, n_full):
     with threadpool_limits(limits=1):
         A = ocpr.Bsr.from_case(case)
         t0 = time.perf_counter()
-        B = ocpr.setup(A)
+        sample_coarse = max(50, int(round(coarse_max * case.n_b / n_full)))
+        B = ocpr.setup(A, oamg.AmgParams(coarse_max=sample_coarse))
         t1 = time.perf_counter()
         res = ofg.fgmres(lambda v: ocpr.bsr_matvec(A, v), B.apply, b, tol=1e-6)
         t2 = time.perf_counter()
@@ -79,16 +84,17 @@ def cpu_baseline(workload, shape_full, gpu_its, n_full):
         "kind": "oracle",
         "extrapolated": True,
         "sample": (f"EXTRAPOLATED: oracle FP64 on the {shape[0]}x{shape[1]}x{shape[2]} grid of the same generator "
-                   f"({case.n_b} cells) on this host, one thread: setup {t1 - t0:.1f} s, solve {t2 - t1:.1f} s, "
-                   f"{res.iterations} its; value = solve time per iteration per cell x {n_full} cells x "
+                   f"({case.n_b} cells, coarsest <= {sample_coarse} rows, {B.amg.n_levels} levels) on this host, "
+                   f"one thread: setup "
+                   f"{t1 - t0:.1f} s, solve {t2 - t1:.1f} s, {res.iterations} its; value = solve time per iteration per cell x {n_full} cells x "
                    f"{gpu_its} GPU FP64 its"),
         "cpu": _cpu_name(),
         "os_cpu_count": os.cpu_count(),
     }
     # the oracle's own full-size solve, measured once by the golden-record
     # script (tests/golden), on the machine named there
-    gname = {"spe10": "oracle_fullsize_spe10.json", "channels": "oracle_fullsize_channels.json"}.get(workload)
-    gpath = os.path.join(ROOT, "tests", "golden", gname) if gname else None
+    suffix = "" if coarse_max == 50 else f"_coarse{coarse_max}"
+    gpath = os.path.join(ROOT, "tests", "golden", f"oracle_fullsize_{workload}{suffix}.json")
     if gpath and os.path.exists(gpath) and tuple(shape_full) == ((60, 220, 85) if workload == "spe10"
                                                                 else (200, 200, 100)):
         with open(gpath) as f:
@@ -251,6 +257,7 @@ KERNEL_SOURCES = {
     "residual_restrict_prolong_level0": ["kernels_amg.hip"] + _COMMON_SRC,
     "residual_restrict_prolong_coarse": ["kernels_amg.hip"] + _COMMON_SRC,
     "tail_vcycle_one_workgroup": ["kernels_tail.hip"] + _COMMON_SRC,
+    "coarsest_inverse_gemv": ["kernels_amli.hip"] + _COMMON_SRC,
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_spe10_3.28M_fp32.json")
 
@@ -265,14 +272,16 @@ def _source_hash(fnames):
     return h.hexdigest()[:16]
 
 
-def _measured_traffic(kernel, workload):
+def _measured_traffic(kernel, workload, amg):
     """HBM bytes per launch of a kernel class from the committed counter
-    summary, if it was taken on this workload and on the current sources of
-    the class (else None)."""
+    summary, if it was taken on this workload, with this AMG configuration and
+    on the current sources of the class (else None)."""
     if workload != "spe10" or not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
         data = json.load(f)
+    if data.get("amg") != amg:
+        return None
     rec = data.get("classes", {}).get(kernel)
     if not rec or rec.get("source_sha256_16") != _source_hash(KERNEL_SOURCES[kernel]):
         return None
@@ -282,6 +291,8 @@ def _measured_traffic(kernel, workload):
 SECOND_STAGES = {"bgs": 0, "bilu": 1}
 DECOUPLINGS = {"none": 0, "quasi-impes": 1, "abf": 2}
 SMOOTHERS = {"pgs-scm": 0, "pgs-no": 1}
+COARSE_SOLVERS = {"lu": 0, "inverse": 1}
+RS_COARSE_MAX = {"lu": 50, "inverse": 4000}
 
 
 def _params(args, **kw):
@@ -301,6 +312,13 @@ def _params(args, **kw):
     if getattr(args, "amg", "rs") == "ua":
         kw.setdefault("amg_kind", 1)
         kw.setdefault("coarse_max", 10000)  # the paper's coarsest size
+    else:
+        # the RS V-cycle solves a coarsest level of thousands of rows directly,
+        # as the paper does (its 10000 measured 3% slower here: a larger dense
+        # product and a longer SETUP); the LU variant keeps 50 rows
+        solver = getattr(args, "coarse_solver", None) or "inverse"
+        kw.setdefault("coarse_solver", COARSE_SOLVERS[solver])
+        kw.setdefault("coarse_max", RS_COARSE_MAX[solver])
     if getattr(args, "coarse_max", None) is not None:
         kw["coarse_max"] = args.coarse_max
     return Params(**kw)
@@ -316,7 +334,8 @@ def _method_config(args):
     p = _params(args)
     smoother = ("PGS-SCM theta=%g" % p.theta_color if p.smoother == 0
                 else "PGS-NO %d chunks" % p.smoother_chunks)
-    amg = (f"RS theta=0.25, V-cycle, coarse<={p.coarse_max}" if p.amg_kind == 0 else
+    coarse = "LU" if p.coarse_solver == 0 else "explicit inverse"
+    amg = (f"RS theta=0.25, V-cycle, coarse<={p.coarse_max} ({coarse})" if p.amg_kind == 0 else
            f"UA-AMG {p.npair}x pairwise matching beta={p.pair_beta}, nonlinear AMLI-cycle ({p.amli_inner} GCR steps), "
            f"coarse<={p.coarse_max} (explicit inverse)")
     return {"amg": f"{amg}, {smoother}, 2+2 sweeps",
@@ -357,14 +376,14 @@ def newton_bench(args):
     dev = torch.device("cuda:0")
     out = {"metric": "Newton sequence: SetupCalls, iterations, time", "config": {
         "workload": f"spe10-like {shape[0]}x{shape[1]}x{shape[2]}, {len(steps)} Jacobians, +-5% drift per step",
-        "rule": "rebuild iff It > 1.3 It_ref", "tol": args.tol}, "data": "synthetic"}
+        "rule": "rebuild iff It > 1.3 It_ref", "tol": args.tol, **_method_config(args)}, "data": "synthetic"}
     for fp32 in (False, True):
         rows = []
         c0 = steps[0][1]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         S = Solver(torch.as_tensor(c0.row_ptr, device=dev), torch.as_tensor(c0.col, device=dev),
-                   torch.as_tensor(c0.vals.reshape(-1), device=dev), Params(precond_fp32=fp32))
+                   torch.as_tensor(c0.vals.reshape(-1), device=dev), _params(args, precond_fp32=fp32))
         torch.cuda.synchronize()
         first_setup = time.perf_counter() - t0
         total = first_setup
@@ -507,6 +526,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-extra-legs", action="store_true",
+                    help="time only the configured solve (no colouring-threshold or coarsest-level comparison legs)")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="launch a 1 GiB plain copy kernel three times first (counter calibration)")
     ap.add_argument("--newton", action="store_true", help="run the Newton-sequence benchmark instead")
@@ -535,8 +556,10 @@ def main():
     ap.add_argument("--amg", choices=("rs", "ua"), default="rs",
                     help="pressure AMG: Ruge-Stueben V-cycle or the paper's UA-AMG with the AMLI-cycle")
     ap.add_argument("--coarse-max", type=int, default=None, help="coarsest AMG size")
+    ap.add_argument("--coarse-solver", choices=sorted(COARSE_SOLVERS), default=None,
+                    help="RS coarsest level: LU in the one-workgroup kernel or the explicit inverse")
     args = ap.parse_args()
-    if args.tuned_theta is not None and args.tuned_theta < 0:
+    if (args.tuned_theta is not None and args.tuned_theta < 0) or args.no_extra_legs:
         args.tuned_theta = None
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solve of one Jacobian is not "
@@ -648,12 +671,16 @@ def main():
 
     kernels = {}
     prof_total = r32["prof"].pop("total_ms")
+    p_run = _params(args)
     for k, (n, ms, by) in r32["prof"].items():
         if n == 0:
             continue
         avg_ms = ms / n
         gbs = by / n / (avg_ms * 1e-3) / 1e9
-        kernels[KERNEL_NAMES[k]] = {"launches": n, "avg_us": avg_ms * 1e3, "bytes_per_launch": by / n,
+        name = KERNEL_NAMES[k]
+        if k == 6 and (p_run.coarse_solver == 1 or p_run.amg_kind == 1):
+            name = "coarsest_inverse_gemv"  # the timer class of the coarsest solve
+        kernels[name] = {"launches": n, "avg_us": avg_ms * 1e3, "bytes_per_launch": by / n,
                                     "achieved_GBs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
                                     "share_of_profiled_solves": ms / prof_total}
     dom = max(kernels, key=lambda k: kernels[k]["share_of_profiled_solves"]) if kernels else None
@@ -661,7 +688,8 @@ def main():
     if dom:
         d = kernels[dom]
         roof = {"bound": "hbm", "kernel": dom, "achieved": d["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": d["achieved_GBs"] / HBM_PEAK_GBS, "traffic": _measured_traffic(dom, args.workload)}
+                "frac": d["achieved_GBs"] / HBM_PEAK_GBS,
+                "traffic": _measured_traffic(dom, args.workload, _method_config(args)["amg"])}
 
     med32 = statistics.median(r32["times"])
     out = {
@@ -697,6 +725,16 @@ def main():
         out.update({"fp64_ms": med64, "fp64_p99_ms": _pct(r64["times"], 0.99),
                     "iterations_fp64": r64["info"]["iterations"], "relres_true_fp64": r64["info"]["relres_true"],
                     "setup_s_fp64": r64["setup_s"], "speedup_fp32_vs_fp64": med64 / med32})
+    if _params(args).coarse_solver == 1 and args.coarse_max is None and not args.no_extra_legs:
+        # the same solve with the 50-row coarsest level LU-solved in the
+        # single-workgroup kernel (three more levels)
+        rc = run(True, max(3, args.steps // 2), 1, coarse_solver=0, coarse_max=RS_COARSE_MAX["lu"])
+        out["rs_coarse50_lu"] = {"coarse_max": RS_COARSE_MAX["lu"], "fp32_ms": statistics.median(rc["times"]),
+                                 "iterations_fp32": rc["info"]["iterations"],
+                                 "relres_true_fp32": rc["info"]["relres_true"],
+                                 "levels": [lv["n"] for lv in rc["levels"]]}
+        print(f"[bench] fp32 precond, coarsest <= 50 by LU: its={rc['info']['iterations']} "
+              f"median={statistics.median(rc['times']):.2f} ms", file=sys.stderr, flush=True)
     if args.tuned_theta is not None:
         # the same solve with another colouring threshold of eq. (strong-matrix)
         # (Section 6 tunes it per problem; 0.05, its choice for SPE10, stays the
@@ -719,7 +757,9 @@ def main():
               f"{sv['solves_per_s']:.1f} solves/s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         its = r64["info"]["iterations"] if r64 else r32["info"]["iterations"]
-        out["cpu_baseline"] = cpu_baseline(args.workload, shape, its, case.n_b)
+        p_rs = _params(args)
+        if p_rs.amg_kind == 0:
+            out["cpu_baseline"] = cpu_baseline(args.workload, shape, its, case.n_b, p_rs.coarse_max)
     print(json.dumps(out), flush=True)
 
 

@@ -122,6 +122,15 @@ typedef struct {
   int32_t amli_inner;     /* flexible GCR steps per coarse correction, 1 or 2 [2] */
   int32_t npair;          /* pairwise matching passes per level [2] */
   double pair_beta;       /* strong-coupling threshold of the matching [0.25] */
+  int32_t coarse_solver;  /* coarsest level of the Ruge-Stueben V-cycle (the paper solves
+                             its coarsest space directly, Section 6): 0 = LU factors
+                             formed on the host (FP64, partial pivoting), forward and
+                             back substitution inside the single-workgroup kernel;
+                             1 = explicit FP64 inverse formed on the GPU at SETUP by
+                             Gauss-Jordan elimination with partial pivoting and applied
+                             as one dense product, which suits a coarsest level of
+                             hundreds to thousands of rows (no single-workgroup kernel
+                             is then used).  The aggregation AMG always uses 1 [0] */
 } cpr_params;
 
 typedef struct {

@@ -73,6 +73,7 @@ class cpr_params(C.Structure):
         ("amli_inner", C.c_int32),
         ("npair", C.c_int32),
         ("pair_beta", C.c_double),
+        ("coarse_solver", C.c_int32),
     ]
 
 

@@ -161,6 +161,7 @@ void cpr_params_default(cpr_params* p) {
   p->amli_inner = 2;
   p->npair = 2;
   p->pair_beta = 0.25;
+  p->coarse_solver = 0;
 }
 
 cpr_status cpr_setup(const cpr_bsr* A, const cpr_params* p, void* hip_stream, cpr_handle** out) {
@@ -180,7 +181,7 @@ cpr_status cpr_setup(const cpr_bsr* A, const cpr_params* p, void* hip_stream, cp
         prm.second_stage < 0 || prm.second_stage > 1 || prm.decoupling < 0 || prm.decoupling > 2 ||
         prm.smoother < 0 || prm.smoother > 1 || prm.smoother_chunks < 1 || prm.amg_kind < 0 || prm.amg_kind > 1 ||
         prm.amli_inner < 1 || prm.amli_inner > 2 || prm.npair < 1 || prm.npair > 4 || !(prm.pair_beta >= 0.0) ||
-        (prm.amg_kind == 1 && prm.smoother != 0))
+        prm.coarse_solver < 0 || prm.coarse_solver > 1 || (prm.amg_kind == 1 && prm.smoother != 0))
       throw Error(CPR_ERR_INVALID_ARG, "invalid parameters");
     h = new cpr_handle();
     h->prm = prm;

@@ -292,8 +292,10 @@ void launch_permute_cols(int n, const double* src, const int32_t* cols, double* 
   CPR_LAUNCH_CHECK();
 }
 
-// x = Ainv b: one wavefront per row, FP64 products summed over the lanes'
-// column ranges, then across lanes in a fixed order.
+// x = Ainv b: one wavefront per row.  Lane l sums the FP64 products of
+// columns l + 64 k into four accumulators by k mod 4 (four independent loads
+// in flight per lane), which are added in a fixed order and then across the
+// lanes in a fixed order, so the result does not depend on the launch.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dense_gemv(int n, const double* __restrict__ ainv,
                                                        const T* __restrict__ b, T* __restrict__ x) {
@@ -301,8 +303,18 @@ __global__ __launch_bounds__(kBlock) void k_dense_gemv(int n, const double* __re
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
   const double* r = ainv + (int64_t)row * n;
-  double acc = 0.0;
-  for (int j = lane; j < n; j += 64) acc = acc + r[j] * (double)b[j];
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int j = lane;
+  for (; j + 192 < n; j += 256) {
+    a0 = a0 + r[j] * (double)b[j];
+    a1 = a1 + r[j + 64] * (double)b[j + 64];
+    a2 = a2 + r[j + 128] * (double)b[j + 128];
+    a3 = a3 + r[j + 192] * (double)b[j + 192];
+  }
+  if (j < n) a0 = a0 + r[j] * (double)b[j];
+  if (j + 64 < n) a1 = a1 + r[j + 64] * (double)b[j + 64];
+  if (j + 128 < n) a2 = a2 + r[j + 128] * (double)b[j + 128];
+  double acc = (a0 + a1) + (a2 + a3);
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) x[row] = (T)acc;
 }

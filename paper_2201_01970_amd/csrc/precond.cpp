@@ -397,6 +397,7 @@ class Precond final : public PrecondBase {
         pgs_no_(prm.smoother == 1),
         chunks_(prm.smoother_chunks),
         ua_(prm.amg_kind == 1),
+        cinv_mode_(prm.amg_kind == 1 || prm.coarse_solver == 1),
         inner_(prm.amli_inner) {
     const int nl = static_cast<int>(hl.size());
     lv_.resize(nl);
@@ -454,12 +455,12 @@ class Precond final : public PrecondBase {
     auto lds_for = [&](int first, int staged) { return tail_layout<T>(hl, first, staged).lds_bytes; };
     tail_ = nl - 1;
     // the one-workgroup tail runs PGS-SCM sweeps of a V-cycle; PGS-NO keeps
-    // every smoothed level on its own kernels; the aggregation AMG's cycle
-    // has no tail (its coarsest level is solved by its inverse)
-    if (ua_) tail_ = nl;
-    if (prm.tail_nnz > 0 && !pgs_no_ && !ua_)
+    // every smoothed level on its own kernels; a coarsest level solved by its
+    // inverse (always for the aggregation AMG) leaves no tail
+    if (cinv_mode_) tail_ = nl;
+    if (prm.tail_nnz > 0 && !pgs_no_ && !cinv_mode_)
       while (tail_ > 0 && hl[tail_ - 1].A.nnz() <= prm.tail_nnz && lds_for(tail_ - 1, nl) <= lds_limit) --tail_;
-    if (!ua_ && lds_for(tail_, nl) > lds_limit)
+    if (!cinv_mode_ && lds_for(tail_, nl) > lds_limit)
       throw Error(CPR_ERR_INVALID_ARG, "the coarsest level does not fit one workgroup's LDS (lower coarse_max)");
     // the sweep matrices staged in LDS: as many levels, coarsest first, as fit
     int staged = nl - 1;
@@ -583,8 +584,9 @@ class Precond final : public PrecondBase {
       }
     }
     nL_ = lv_.back().n;
-    if (ua_) build_amli(lu, s);  // coarsest inverse and the GCR buffers; no tail kernel
-    if (!ua_) {
+    if (cinv_mode_) build_coarse_inverse(lu, s);  // no tail kernel
+    if (ua_) build_gcr();
+    if (!cinv_mode_) {
     lu_ = ar_.upload(lu);
     // compose the factorisation's row swaps: (P b)_i = b[rperm[i]]
     std::vector<int32_t> rperm(piv.size());
@@ -883,7 +885,7 @@ class Precond final : public PrecondBase {
       vcycle(l, s, first_done);
   }
 
-  // The coarsest level of the aggregation AMG: x = A_L^{-1} b.
+  // The coarsest level solved by its explicit inverse: x = A_L^{-1} b.
   void coarse_solve(hipStream_t s) {
     Level& L = lv_.back();
     if (timer) timer->begin(CPR_KSTAT_TAIL, s);
@@ -960,12 +962,10 @@ class Precond final : public PrecondBase {
     if (timer) timer->end(kind, s, 13.0 * n * sizeof(T));
   }
 
-  // The aggregation AMG's SETUP on the device: the explicit inverse of the
-  // coarsest matrix (dense, row-major) by Gauss-Jordan elimination with
-  // partial pivoting in SETUP-only memory, and the GCR vectors of every level
-  // that gets a coarse correction by GCR.
-  void build_amli(const std::vector<double>& dense, hipStream_t s) {
-    const int nl = static_cast<int>(lv_.size());
+  // The explicit inverse of the coarsest matrix (dense, row-major) by
+  // Gauss-Jordan elimination with partial pivoting on the device, in
+  // SETUP-only memory; only the inverse stays resident.
+  void build_coarse_inverse(const std::vector<double>& dense, hipStream_t s) {
     const int n = nL_;
     Arena work;  // released when SETUP returns
     double* a = work.upload(dense);
@@ -988,6 +988,12 @@ class Precond final : public PrecondBase {
     cinv_ = ar_.alloc<double>(static_cast<int64_t>(n) * n);
     launch_permute_cols(n, a, dcols, cinv_, s);
     HIPCHK(hipStreamSynchronize(s));
+  }
+
+  // The GCR vectors of every level of the AMLI-cycle that gets a coarse
+  // correction by GCR.
+  void build_gcr() {
+    const int nl = static_cast<int>(lv_.size());
     gcr_.resize(nl);
     for (int c = 1; c + 1 < nl; ++c) {
       Gcr& g = gcr_[c];
@@ -1006,6 +1012,10 @@ class Precond final : public PrecondBase {
   void vcycle(int l, hipStream_t s, bool first_done) {
     Level& L = lv_[l];
     const int nl = static_cast<int>(lv_.size());
+    if (cinv_mode_ && l == nl - 1) {
+      coarse_solve(s);
+      return;
+    }
     if (l == tail_) {
       if (timer) timer->begin(CPR_KSTAT_TAIL, s);
       launch_tail_vcycle<T>(tail_dev_, nl - tail_, pre_, post_, nL_, lu_, tail_img_, tail_lay_, s);
@@ -1080,6 +1090,7 @@ class Precond final : public PrecondBase {
     double *part = nullptr, *part2 = nullptr, *scal = nullptr;
   };
   bool ua_ = false;
+  bool cinv_mode_ = false;  // the coarsest level is solved by its explicit inverse
   int inner_ = 2;
   double* cinv_ = nullptr;
   std::vector<Gcr> gcr_;

@@ -341,17 +341,18 @@ void cpr_handle::build_precond() {
       std::iota(L.perm.begin(), L.perm.end(), 0);
     }
   }
-  // coarsest level, dense (FP64): LU-factored here for the V-cycle; for the
-  // aggregation AMG left unfactored (its inverse is formed on the device)
+  // coarsest level, dense (FP64): LU-factored here for the single-workgroup
+  // kernel; left unfactored when its inverse is formed on the device
+  const bool coarse_inverse = prm.amg_kind == 1 || prm.coarse_solver == 1;
   const HostCsr& Ac = hl.back().A;
   const int32_t nc = Ac.n_rows;
-  if (nc > (prm.amg_kind == 1 ? 16384 : 8192))
+  if (nc > (coarse_inverse ? 16384 : 8192))
     throw Error(CPR_ERR_INVALID_ARG, "the coarsest level has " + std::to_string(nc) + " rows (coarsening stalled)");
   std::vector<double> lu(static_cast<size_t>(nc) * nc, 0.0);
   for (int32_t i = 0; i < nc; ++i)
     for (int32_t q = Ac.ptr[i]; q < Ac.ptr[i + 1]; ++q) lu[static_cast<size_t>(i) * nc + Ac.col[q]] += Ac.val[q];
   std::vector<int32_t> piv;
-  if (prm.amg_kind == 0 && !dense_lu(nc, lu, piv))
+  if (!coarse_inverse && !dense_lu(nc, lu, piv))
     throw Error(CPR_ERR_SINGULAR_COARSE, "coarsest matrix is singular");
 
   // stage-2 block colouring or factorisation (computed on its own thread since the start)

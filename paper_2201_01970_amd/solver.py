@@ -39,6 +39,7 @@ class Params:
     amli_inner: int = 2
     npair: int = 2
     pair_beta: float = 0.25
+    coarse_solver: int = 0  # RS coarsest: 0 LU in the one-workgroup kernel, 1 explicit inverse (dense product)
 
     def to_c(self) -> A.cpr_params:
         p = A.cpr_params()

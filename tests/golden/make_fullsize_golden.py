@@ -9,6 +9,10 @@ seeded sample of unknowns.  Only ``oracle/`` and ``workloads/`` are used.
 
     python tests/golden/make_fullsize_golden.py spe10      # 3.28M DOF
     python tests/golden/make_fullsize_golden.py channels   # 12M DOF
+    python tests/golden/make_fullsize_golden.py spe10 4000 # coarsest level <= 4000 rows
+
+With a second argument the AMG coarsens down to that many rows (the default
+is 50) and the file name carries it (oracle_fullsize_spe10_coarse4000.json).
 
 Single-threaded (BLAS limited to one thread), so the recorded wall times are
 the oracle's one-core times on the machine that ran the script.
@@ -50,8 +54,10 @@ def sample_dofs(ndof, seed):
     return np.sort(np.concatenate([idx, [0, ndof - 1]])).astype(np.int64)
 
 
-def main(which):
+def main(which, coarse_max=None):
     from threadpoolctl import threadpool_limits
+
+    from oracle import amg
 
     if which == "spe10":
         case = bo.case_spe10_like(seed=1100)
@@ -63,7 +69,9 @@ def main(which):
         desc = "channelised 200x200x100 (seed 1400, RHS 1401)"
     else:
         raise SystemExit(f"unknown workload {which}")
-    out = {"workload": desc, "n_b": int(case.n_b), "nnz_b": int(case.nnz_b), "tol": 1e-6, "restart": 30}
+    amg_params = amg.AmgParams() if coarse_max is None else amg.AmgParams(coarse_max=coarse_max)
+    out = {"workload": desc, "n_b": int(case.n_b), "nnz_b": int(case.nnz_b), "tol": 1e-6, "restart": 30,
+           "coarse_max": int(amg_params.coarse_max)}
     print(f"[golden] {desc}: n_b={case.n_b} nnz_b={case.nnz_b}", flush=True)
     with threadpool_limits(limits=1):
         A = cpr.Bsr.from_case(case)
@@ -71,7 +79,7 @@ def main(which):
         for name, dt in (("fp64", np.float64), ("fp32_model", np.float32)):
             t0 = time.perf_counter()
             if B64 is None:
-                B = B64 = cpr.setup(A, dtype=dt)
+                B = B64 = cpr.setup(A, amg_params, dtype=dt)
             else:  # the float32 model applies the same SETUP products in float32
                 B = dataclasses.replace(B64, dtype=dt)
             t1 = time.perf_counter()
@@ -93,11 +101,12 @@ def main(which):
             out[name] = rec
     out["cpu"] = _cpu_name()
     out["cores"] = 1
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_fullsize_{which}.json")
+    suffix = "" if coarse_max is None else f"_coarse{coarse_max}"
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_fullsize_{which}{suffix}.json")
     with open(path, "w") as f:
         json.dump(out, f)
     print(f"[golden] wrote {path}", flush=True)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "spe10")
+    main(sys.argv[1] if len(sys.argv) > 1 else "spe10", int(sys.argv[2]) if len(sys.argv) > 2 else None)

@@ -199,17 +199,20 @@ def _golden(which):
         return json.load(f)
 
 
-def _check_against_golden(case, b, g, tag):
+def _check_against_golden(case, b, g, tag, **params):
     from paper_2201_01970_amd import Params, Solver
 
     assert g["n_b"] == case.n_b and g["nnz_b"] == case.nnz_b
     idx = np.asarray(g["fp64"]["sample_dof"], dtype=np.int64)
     gx = np.asarray(g["fp64"]["sample_x"])
     for fp32 in (False, True):
-        S = Solver(_dev(case.row_ptr), _dev(case.col), _dev(case.vals.reshape(-1)), Params(precond_fp32=fp32))
+        S = Solver(_dev(case.row_ptr), _dev(case.col), _dev(case.vals.reshape(-1)),
+                   Params(precond_fp32=fp32, **params))
         x, info = S.solve(_dev(b), tol=1e-6)
+        n_levels = S.level_info(0)["n_levels"]
         x = x.cpu().numpy()
         S.close()
+        assert n_levels == g["fp64"]["n_levels"]
         d = np.linalg.norm(x[idx] - gx) / np.linalg.norm(gx)
         dn = abs(np.linalg.norm(x) - g["fp64"]["x_norm"]) / g["fp64"]["x_norm"]
         print(f"[{tag}] fp32={fp32} gpu its={info['iterations']} relres={info['relres_true']:.3e} | oracle fp64 "
@@ -228,6 +231,18 @@ def _check_against_golden(case, b, g, tag):
 def test_fullsize_solve_matches_oracle_golden(big):
     case, b = big
     _check_against_golden(case, b, _golden("spe10"), "fullsize vs oracle")
+
+
+def test_fullsize_coarse_inverse_matches_oracle_golden(big):
+    """The configuration the benchmark times by default: the RS hierarchy
+    coarsened to at most 4000 rows (8 levels, a 3702-row coarsest level
+    solved by its explicit inverse), against the oracle's solve with the same
+    hierarchy and its LU-solved coarsest level
+    (tests/golden/make_fullsize_golden.py spe10 4000)."""
+    case, b = big
+    g = _golden("spe10_coarse4000")
+    assert g["coarse_max"] == 4000
+    _check_against_golden(case, b, g, "fullsize coarse<=4000 inverse vs oracle", coarse_max=4000, coarse_solver=1)
 
 
 def test_fullsize_bilu_second_stage_bit_exact(big):
