@@ -263,11 +263,14 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_spe10_3.28M_fp32.json
 
 
 def _source_hash(fnames):
+    """SHA-256 (16 hex digits) of a kernel class's sources and of the build
+    script that fixes its compiler flags."""
     import hashlib
 
     h = hashlib.sha256()
-    for fname in fnames:
-        with open(os.path.join(ROOT, "paper_2201_01970_amd", "csrc", fname), "rb") as f:
+    paths = [os.path.join(ROOT, "paper_2201_01970_amd", "csrc", f) for f in fnames]
+    for path in paths + [os.path.join(ROOT, "paper_2201_01970_amd", "build.py")]:
+        with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 

@@ -40,6 +40,10 @@ COMMON = [
     "-ffp-contract=off",
     # packed FP32 instructions stay disabled in every device code object
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # kernel arguments preloaded into SGPRs at wave launch (gfx950), so a
+    # kernel's first loads do not wait for its argument block (FP32 solve
+    # at 3.28M DOF 11.40 -> 11.34 ms)
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
     "-Wall", "-Wno-unused-result",
     f"-I{os.path.join(ROOT, 'include')}",
 ]

@@ -154,3 +154,61 @@ def test_rejects_bad_coarse_solver():
     case = bo.case_small()
     with pytest.raises(CprError):
         _solver(case, coarse_solver=2)
+
+
+def test_single_level_hierarchy_is_a_direct_solve():
+    """coarse_max above the pressure size: the hierarchy is one level, the
+    V-cycle is x = A_P^{-1} b (no smoothing), and CPR-FGMRES takes the
+    oracle's iterations with the iterate within 1e-10.  The explicit inverse
+    and LAPACK's solve differ by rounding amplified by the condition number
+    of A_P (a nearly singular pressure matrix: accumulation terms of 3e-6
+    against transmissibilities of 1e-3..1e-1), so the V-cycle bound is
+    100 eps cond(A_P)."""
+    case = bo.case_small()
+    A = cpr.Bsr.from_case(case)
+    b = bo.rhs(case.ndof, 1001)
+    B = cpr.setup(A, amg.AmgParams(coarse_max=10 ** 6))
+    assert B.amg.n_levels == 1
+    S = _solver(case, coarse_max=10 ** 6, coarse_solver=1)
+    assert S.level_info(0)["n_levels"] == 1
+    rng = np.random.default_rng(29)
+    r = rng.standard_normal(A.n_b)
+    got = S.vcycle(_dev(r)).cpu().numpy()
+    Ad = B.amg.levels[0].A.to_dense()
+    want = np.linalg.solve(Ad, r)
+    bound = 100 * np.finfo(np.float64).eps * np.linalg.cond(Ad)
+    d = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(f"[direct] cond {np.linalg.cond(Ad):.2e}: vcycle diff {d:.2e}, bound {bound:.2e}", flush=True)
+    assert d <= bound
+    res = fgmres.fgmres(lambda v: cpr.bsr_matvec(A, v), B.apply, b, tol=1e-6)
+    x, info = S.solve(_dev(b), tol=1e-6)
+    S.close()
+    assert info["iterations"] == res.iterations
+    assert np.linalg.norm(x.cpu().numpy() - res.x) <= 1e-10 * np.linalg.norm(res.x)
+
+
+def test_newton_sequence_with_inverse_matches_oracle():
+    """ASCPR over a drifting Newton sequence with the inverse path (rule
+    It^(k-1) <= mu, mu = 7, so the sequence both reuses and rebuilds): each
+    SETUP forms a new coarsest inverse in fresh SETUP memory, a reused B keeps
+    the old one; rebuild flags and iterations equal the oracle's
+    solve_sequence step by step, iterates within 1e-10."""
+    from oracle import ascpr
+
+    seq = list(bo.newton_sequence(n_steps=5, base_seed=1110, seed=1210, shape=(30, 40, 20), amp=0.2))
+    steps = [(cpr.Bsr.from_case(c), b) for _, c, b in seq]
+    reps = ascpr.solve_sequence(steps, amg.AmgParams(coarse_max=2500), mode="mu", mu=7)
+    c0 = seq[0][1]
+    S = _solver(c0, coarse_max=2500, coarse_solver=1, reuse_mode=1, mu=7)
+    for k, ((_, case, b), rep) in enumerate(zip(seq, reps)):
+        if k > 0:
+            S.update_values(_dev(case.vals.reshape(-1)))
+        x, info = S.solve(_dev(b), tol=1e-6)
+        rebuilt = bool(info["rebuilt"]) or k == 0
+        print(f"[inverse newton] step {k}: gpu its={info['iterations']} rebuilt={rebuilt} | "
+              f"oracle its={rep.iterations} rebuilt={rep.rebuilt}", flush=True)
+        assert rebuilt == rep.rebuilt, k
+        assert info["iterations"] == rep.iterations, k
+        assert np.linalg.norm(x.cpu().numpy() - rep.x) <= 1e-10 * np.linalg.norm(rep.x), k
+    S.close()
+    assert any(r.rebuilt for r in reps[1:]) and not all(r.rebuilt for r in reps[1:])
