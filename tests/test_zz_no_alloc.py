@@ -69,7 +69,9 @@ def test_two_calls_in_a_row_second_smaller():
     S_small.close()
 
 
-@pytest.mark.parametrize("kw", [dict(restart=4), dict(precond_fp32=1)], ids=["restart4", "fp32"])
+@pytest.mark.parametrize("kw", [dict(restart=4), dict(precond_fp32=1),
+                                dict(precond_fp32=1, coarse_max=120, coarse_solver=1)],
+                         ids=["restart4", "fp32", "fp32-coarse-inverse"])
 def test_restarted_and_fp32(kw):
     case = bo.case_small(seed=21, shape=(14, 12, 6))
     b = bo.rhs(case.ndof, 22)
