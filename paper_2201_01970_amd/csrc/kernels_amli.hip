@@ -203,21 +203,30 @@ CPR_GCR_INST(float)
 
 // ------------------------------------------------ coarsest level: dense inverse
 // In-place Gauss-Jordan elimination with partial pivoting on the row-major
-// n x n matrix a, step k.  Pivot search, row swap, multiplier column and the
+// n x n matrix a, step k.  Column k of the matrix before step k is kept
+// contiguous in cur[0..n) (written by the previous step, so the pivot search
+// reads it without striding through a).  Pivot search, row swap and the
 // scaling of the pivot row run in one workgroup; the elimination of the other
-// rows in a second kernel.  After step k, row k holds (row k)/pivot with entry
-// k = 1/pivot, and every other row i has had m_i (its old entry k) times the
-// new row k subtracted, entry k becoming -m_i/pivot.
+// rows in a second kernel, which also leaves column k+1 in nxt.  After step k,
+// row k holds (row k)/pivot with entry k = 1/pivot, and every other row i has
+// had m_i (its old entry k) times the new row k subtracted, entry k becoming
+// -m_i/pivot.
 constexpr int kGjBlock = 1024;
 
+__global__ __launch_bounds__(kBlock) void k_gj_column(int n, const double* __restrict__ a, double* __restrict__ col) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) col[i] = a[(int64_t)i * n];
+}
+
 __global__ __launch_bounds__(kGjBlock) void k_gj_pivot(int n, int k, double* __restrict__ a, int32_t* __restrict__ piv,
-                                                       double* __restrict__ m, int32_t* __restrict__ bad) {
+                                                       double* __restrict__ cur, double* __restrict__ nxt,
+                                                       int32_t* __restrict__ bad) {
   __shared__ double sv[kGjBlock];
   __shared__ int si[kGjBlock];
   double best = -1.0;
   int bi = n;
   for (int i = k + (int)threadIdx.x; i < n; i += kGjBlock) {
-    const double v = fabs(a[(int64_t)i * n + k]);
+    const double v = fabs(cur[i]);
     if (v > best) {  // rows visited in ascending order: ties keep the smallest index
       best = v;
       bi = i;
@@ -239,19 +248,26 @@ __global__ __launch_bounds__(kGjBlock) void k_gj_pivot(int n, int k, double* __r
   }
   const int p = si[0];
   const bool ok = p < n && sv[0] > 0.0;
-  if (p < n && p != k)
+  if (p < n && p != k) {
     for (int j = threadIdx.x; j < n; j += kGjBlock) {
       const double t = a[(int64_t)k * n + j];
       a[(int64_t)k * n + j] = a[(int64_t)p * n + j];
       a[(int64_t)p * n + j] = t;
     }
+    if (threadIdx.x == 0) {
+      const double t = cur[k];
+      cur[k] = cur[p];
+      cur[p] = t;
+    }
+  }
   __syncthreads();
   const double pv = ok ? a[(int64_t)k * n + k] : 1.0;
-  for (int i = threadIdx.x; i < n; i += kGjBlock) m[i] = a[(int64_t)i * n + k];
   __syncthreads();
   for (int j = threadIdx.x; j < n; j += kGjBlock) {
     const double v = j == k ? 1.0 : a[(int64_t)k * n + j];
-    a[(int64_t)k * n + j] = v / pv;
+    const double r = v / pv;
+    a[(int64_t)k * n + j] = r;
+    if (j == k + 1) nxt[k] = r;
   }
   if (threadIdx.x == 0) {
     piv[k] = ok ? p : k;
@@ -260,16 +276,24 @@ __global__ __launch_bounds__(kGjBlock) void k_gj_pivot(int n, int k, double* __r
 }
 
 __global__ __launch_bounds__(kBlock) void k_gj_eliminate(int n, int k, double* __restrict__ a,
-                                                         const double* __restrict__ m) {
+                                                         const double* __restrict__ cur, double* __restrict__ nxt) {
   const int i = blockIdx.x;
   if (i == k) return;
-  const double f = m[i];
+  const double f = cur[i];
   double* row = a + (int64_t)i * n;
+  // a zero multiplier leaves the row as it is (the coarsest Galerkin matrix
+  // is sparse, so most rows of the early steps have nothing to eliminate)
+  if (f == 0.0) {
+    if (threadIdx.x == 0 && k + 1 < n) nxt[i] = row[k + 1];
+    return;
+  }
   const double* rk = a + (int64_t)k * n;
   for (int j = threadIdx.x; j < n; j += kBlock) {
     const double v = j == k ? 0.0 : row[j];
     const double prod = f * rk[j];
-    row[j] = v - prod;
+    const double r = v - prod;
+    row[j] = r;
+    if (j == k + 1) nxt[i] = r;
   }
 }
 
@@ -280,10 +304,16 @@ __global__ __launch_bounds__(kBlock) void k_permute_cols(int n, const double* __
   for (int j = threadIdx.x; j < n; j += kBlock) dst[(int64_t)i * n + j] = src[(int64_t)i * n + cols[j]];
 }
 
-void launch_gj_step(int n, int k, double* a, int32_t* piv, double* m, int32_t* bad, hipStream_t s) {
-  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kGjBlock), 0, s, n, k, a, piv, m, bad);
+void launch_gj_step(int n, int k, double* a, int32_t* piv, double* col2, int32_t* bad, hipStream_t s) {
+  double* cur = col2 + (int64_t)(k & 1) * n;
+  double* nxt = col2 + (int64_t)((k + 1) & 1) * n;
+  if (k == 0) {
+    hipLaunchKernelGGL(k_gj_column, dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, a, cur);
+    CPR_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kGjBlock), 0, s, n, k, a, piv, cur, nxt, bad);
   CPR_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_gj_eliminate, dim3(n), dim3(kBlock), 0, s, n, k, a, m);
+  hipLaunchKernelGGL(k_gj_eliminate, dim3(n), dim3(kBlock), 0, s, n, k, a, cur, nxt);
   CPR_LAUNCH_CHECK();
 }
 

@@ -346,8 +346,11 @@ void cpr_handle::build_precond() {
   const bool coarse_inverse = prm.amg_kind == 1 || prm.coarse_solver == 1;
   const HostCsr& Ac = hl.back().A;
   const int32_t nc = Ac.n_rows;
-  if (nc > (coarse_inverse ? 16384 : 8192))
-    throw Error(CPR_ERR_INVALID_ARG, "the coarsest level has " + std::to_string(nc) + " rows (coarsening stalled)");
+  const int32_t dense_max = coarse_inverse ? 16384 : 8192;
+  if (nc > dense_max)
+    throw Error(CPR_ERR_INVALID_ARG, "the coarsest level has " + std::to_string(nc) + " rows, more than the " +
+                                         std::to_string(dense_max) +
+                                         " its dense direct solve takes (coarsening stalled, or coarse_max too large)");
   std::vector<double> lu(static_cast<size_t>(nc) * nc, 0.0);
   for (int32_t i = 0; i < nc; ++i)
     for (int32_t q = Ac.ptr[i]; q < Ac.ptr[i + 1]; ++q) lu[static_cast<size_t>(i) * nc + Ac.col[q]] += Ac.val[q];

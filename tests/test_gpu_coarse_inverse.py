@@ -212,3 +212,14 @@ def test_newton_sequence_with_inverse_matches_oracle():
         assert np.linalg.norm(x.cpu().numpy() - rep.x) <= 1e-10 * np.linalg.norm(rep.x), k
     S.close()
     assert any(r.rebuilt for r in reps[1:]) and not all(r.rebuilt for r in reps[1:])
+
+
+@pytest.mark.parametrize("solver", [0, 1])
+def test_oversized_coarsest_is_refused(solver):
+    """A coarsest level beyond the dense direct solve's limit (8192 rows by
+    LU, 16384 by the inverse) is refused at SETUP with CPR_ERR_INVALID_ARG."""
+    from paper_2201_01970_amd import CprError
+
+    case = bo.case_spe10_like(seed=1110, shape=(30, 40, 20))  # 23400 pressure rows
+    with pytest.raises(CprError, match="dense direct solve"):
+        _solver(case, coarse_max=10 ** 6, coarse_solver=solver)
