@@ -24,8 +24,9 @@ preconditioner):
   D_i^{-1} the inverse of the diagonal block (LU with partial pivoting).
 * Block products y_i[r] = sum over blocks in stored order of
   a[r][0]*x0 + a[r][1]*x1 + a[r][2]*x2, added one product at a time.
-* ``decoupling`` (the survey's next step beyond the paper, which leaves the
-  well and decoupling details out): a block-diagonal W is applied to the
+* ``decoupling`` (for the full system with wells of eq. (Jacobian-system);
+  the paper leaves the well and decoupling details out, Section 2.2): a
+  block-diagonal W is applied to the
   rows before anything else, and B is built on W A: "quasi-impes" takes
   W_i = I with (0,1) = -D_01/D_11 and (0,2) = -D_02/D_22 (the pressure row
   loses the saturation derivatives of its own diagonal block, using diagonal
