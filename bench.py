@@ -371,7 +371,7 @@ def newton_bench(args):
     preconditioners; per step: iterations, rebuild flag, true relres, times."""
     import torch
 
-    from paper_2201_01970_amd import Params, Solver
+    from paper_2201_01970_amd import Solver
     from workloads import blackoil as bo
 
     shape = tuple(args.shape) if args.shape else (60, 220, 85)
@@ -431,7 +431,7 @@ def experiments_bench(args):
     import numpy as np
     import torch
 
-    from paper_2201_01970_amd import Params, Solver
+    from paper_2201_01970_amd import Solver
     from workloads import blackoil as bo
 
     dev = torch.device("cuda:0")
@@ -443,7 +443,8 @@ def experiments_bench(args):
     vals = torch.as_tensor(case.vals.reshape(-1), device=dev)
     out = {"metric": "Section 6 experiment shapes: theta_c, launch shape, PGS-NO chunks, reuse threshold mu",
            "config": {"workload": f"spe10-like {shape[0]}x{shape[1]}x{shape[2]}", "tol": args.tol,
-                      "precond": "FP32 preconditioner, FP64 FGMRES(30)"}, "data": "synthetic"}
+                      "precond": "FP32 preconditioner, FP64 FGMRES(30)", **_method_config(args)},
+           "data": "synthetic"}
 
     def timed(p, reps=3):
         S = Solver(rp, col, vals, p)
@@ -464,9 +465,9 @@ def experiments_bench(args):
 
     rows = []
     for theta in (0.0, 0.05, 0.1, 0.3):
-        for shape_kw in (dict(row_layout=0), dict(row_layout=1), dict(row_layout=2), dict(row_layout=16),
-                         dict(tail_nnz=0)):
-            r = timed(Params(precond_fp32=True, theta_color=theta, **shape_kw))
+        for shape_kw in (dict(row_layout=0), dict(row_layout=1), dict(row_layout=2), dict(row_layout=4),
+                         dict(row_layout=16)):
+            r = timed(_params(args, precond_fp32=True, theta_color=theta, **shape_kw))
             r.update(theta_color=theta, **shape_kw)
             rows.append(r)
             print(f"[exp] theta {theta} {shape_kw}: its {r['iterations']} {r['median_ms']:.2f} ms "
@@ -477,7 +478,7 @@ def experiments_bench(args):
 
     rows = []
     for chunks in (1024, 4096, 16384, 65536, 262144):
-        r = timed(Params(precond_fp32=True, smoother=1, smoother_chunks=chunks), reps=1)
+        r = timed(_params(args, precond_fp32=True, smoother=1, smoother_chunks=chunks), reps=1)
         r.update(chunks=chunks)
         rows.append(r)
         print(f"[exp] pgs-no {chunks}: its {r['iterations']} {r['median_ms']:.2f} ms", file=sys.stderr, flush=True)
@@ -491,7 +492,7 @@ def experiments_bench(args):
             v0 = torch.as_tensor(steps[0][1], device=dev)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            S = Solver(rp, col, v0, Params(precond_fp32=True, reuse_mode=1, mu=mu))
+            S = Solver(rp, col, v0, _params(args, precond_fp32=True, reuse_mode=1, mu=mu))
             torch.cuda.synchronize()
             first = time.perf_counter() - t0
             total, setups, setup_ms, its = first, 1, first * 1e3, []
@@ -591,7 +592,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2201_01970_amd import Params, Solver
+    from paper_2201_01970_amd import Solver
     from paper_2201_01970_amd import _capi as capi
 
     dev = torch.device("cuda:0")
