@@ -12,7 +12,9 @@ seeded sample of unknowns.  Only ``oracle/`` and ``workloads/`` are used.
     python tests/golden/make_fullsize_golden.py spe10 4000 # coarsest level <= 4000 rows
 
 With a second argument the AMG coarsens down to that many rows (the default
-is 50) and the file name carries it (oracle_fullsize_spe10_coarse4000.json).
+is 50) and the file name carries it (oracle_fullsize_spe10_coarse4000.json);
+the second argument "ua" selects the paper's aggregation AMG with the
+AMLI-cycle (coarsest 10000 rows; oracle_fullsize_spe10_ua.json).
 
 Single-threaded (BLAS limited to one thread), so the recorded wall times are
 the oracle's one-core times on the machine that ran the script.
@@ -69,9 +71,14 @@ def main(which, coarse_max=None):
         desc = "channelised 200x200x100 (seed 1400, RHS 1401)"
     else:
         raise SystemExit(f"unknown workload {which}")
-    amg_params = amg.AmgParams() if coarse_max is None else amg.AmgParams(coarse_max=coarse_max)
+    if coarse_max == "ua":
+        from oracle import uaamg
+
+        amg_params = uaamg.UaParams()
+    else:
+        amg_params = amg.AmgParams() if coarse_max is None else amg.AmgParams(coarse_max=coarse_max)
     out = {"workload": desc, "n_b": int(case.n_b), "nnz_b": int(case.nnz_b), "tol": 1e-6, "restart": 30,
-           "coarse_max": int(amg_params.coarse_max)}
+           "coarse_max": int(amg_params.coarse_max), "amg": type(amg_params).__name__}
     print(f"[golden] {desc}: n_b={case.n_b} nnz_b={case.nnz_b}", flush=True)
     with threadpool_limits(limits=1):
         A = cpr.Bsr.from_case(case)
@@ -101,7 +108,7 @@ def main(which, coarse_max=None):
             out[name] = rec
     out["cpu"] = _cpu_name()
     out["cores"] = 1
-    suffix = "" if coarse_max is None else f"_coarse{coarse_max}"
+    suffix = "" if coarse_max is None else ("_ua" if coarse_max == "ua" else f"_coarse{coarse_max}")
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_fullsize_{which}{suffix}.json")
     with open(path, "w") as f:
         json.dump(out, f)
@@ -109,4 +116,5 @@ def main(which, coarse_max=None):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "spe10", int(sys.argv[2]) if len(sys.argv) > 2 else None)
+    arg2 = sys.argv[2] if len(sys.argv) > 2 else None
+    main(sys.argv[1] if len(sys.argv) > 1 else "spe10", arg2 if arg2 in (None, "ua") else int(arg2))

@@ -245,6 +245,19 @@ def test_fullsize_coarse_inverse_matches_oracle_golden(big):
     _check_against_golden(case, b, g, "fullsize coarse<=4000 inverse vs oracle", coarse_max=4000, coarse_solver=1)
 
 
+def test_fullsize_aggregation_amg_matches_oracle_golden(big):
+    """The paper's pressure solver at full size (unsmoothed aggregation with
+    two pairwise-matching passes per level, the nonlinear AMLI-cycle with two
+    GCR steps, coarsest level of at most 10000 rows solved directly) against
+    the oracle's own solve of it (tests/golden/make_fullsize_golden.py spe10
+    ua): the FP64 path takes the oracle's iteration count with the iterate
+    within 1e-10, the FP32 path within 10% of the oracle's iterations."""
+    case, b = big
+    g = _golden("spe10_ua")
+    assert g["amg"] == "UaParams" and g["coarse_max"] == 10000
+    _check_against_golden(case, b, g, "fullsize UA-AMG vs oracle", amg_kind=1, coarse_max=10000)
+
+
 def test_fullsize_bilu_second_stage_bit_exact(big):
     """Block ILU(0) second stage at full size, in the launch configuration the
     benchmark times with --second-stage bilu (363 forward and 363 backward
