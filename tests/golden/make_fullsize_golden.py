@@ -14,7 +14,8 @@ seeded sample of unknowns.  Only ``oracle/`` and ``workloads/`` are used.
 With a second argument the AMG coarsens down to that many rows (the default
 is 50) and the file name carries it (oracle_fullsize_spe10_coarse4000.json);
 the second argument "ua" selects the paper's aggregation AMG with the
-AMLI-cycle (coarsest 10000 rows; oracle_fullsize_spe10_ua.json).
+AMLI-cycle (coarsest 10000 rows; oracle_fullsize_spe10_ua.json), "bilu" the
+block ILU(0) second stage with the default AMG (oracle_fullsize_spe10_bilu.json).
 
 Single-threaded (BLAS limited to one thread), so the recorded wall times are
 the oracle's one-core times on the machine that ran the script.
@@ -71,14 +72,18 @@ def main(which, coarse_max=None):
         desc = "channelised 200x200x100 (seed 1400, RHS 1401)"
     else:
         raise SystemExit(f"unknown workload {which}")
+    second_stage = "bilu" if coarse_max == "bilu" else "bgs"
     if coarse_max == "ua":
         from oracle import uaamg
 
         amg_params = uaamg.UaParams()
+    elif coarse_max == "bilu":
+        amg_params = amg.AmgParams()
     else:
         amg_params = amg.AmgParams() if coarse_max is None else amg.AmgParams(coarse_max=coarse_max)
     out = {"workload": desc, "n_b": int(case.n_b), "nnz_b": int(case.nnz_b), "tol": 1e-6, "restart": 30,
-           "coarse_max": int(amg_params.coarse_max), "amg": type(amg_params).__name__}
+           "coarse_max": int(amg_params.coarse_max), "amg": type(amg_params).__name__,
+           "second_stage": second_stage}
     print(f"[golden] {desc}: n_b={case.n_b} nnz_b={case.nnz_b}", flush=True)
     with threadpool_limits(limits=1):
         A = cpr.Bsr.from_case(case)
@@ -86,7 +91,7 @@ def main(which, coarse_max=None):
         for name, dt in (("fp64", np.float64), ("fp32_model", np.float32)):
             t0 = time.perf_counter()
             if B64 is None:
-                B = B64 = cpr.setup(A, amg_params, dtype=dt)
+                B = B64 = cpr.setup(A, amg_params, dtype=dt, second_stage=second_stage)
             else:  # the float32 model applies the same SETUP products in float32
                 B = dataclasses.replace(B64, dtype=dt)
             t1 = time.perf_counter()
@@ -108,7 +113,7 @@ def main(which, coarse_max=None):
             out[name] = rec
     out["cpu"] = _cpu_name()
     out["cores"] = 1
-    suffix = "" if coarse_max is None else ("_ua" if coarse_max == "ua" else f"_coarse{coarse_max}")
+    suffix = "" if coarse_max is None else (f"_{coarse_max}" if coarse_max in ("ua", "bilu") else f"_coarse{coarse_max}")
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_fullsize_{which}{suffix}.json")
     with open(path, "w") as f:
         json.dump(out, f)
@@ -117,4 +122,4 @@ def main(which, coarse_max=None):
 
 if __name__ == "__main__":
     arg2 = sys.argv[2] if len(sys.argv) > 2 else None
-    main(sys.argv[1] if len(sys.argv) > 1 else "spe10", arg2 if arg2 in (None, "ua") else int(arg2))
+    main(sys.argv[1] if len(sys.argv) > 1 else "spe10", arg2 if arg2 in (None, "ua", "bilu") else int(arg2))

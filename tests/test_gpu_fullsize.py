@@ -258,6 +258,17 @@ def test_fullsize_aggregation_amg_matches_oracle_golden(big):
     _check_against_golden(case, b, g, "fullsize UA-AMG vs oracle", amg_kind=1, coarse_max=10000)
 
 
+def test_fullsize_bilu_solve_matches_oracle_golden(big):
+    """The paper's second stage (block ILU(0), level-scheduled solves) in the
+    whole solve at full size, against the oracle's own solve with it
+    (tests/golden/make_fullsize_golden.py spe10 bilu): the oracle's iteration
+    count and the iterate within 1e-10 in FP64, FP32 within 10%."""
+    case, b = big
+    g = _golden("spe10_bilu")
+    assert g["second_stage"] == "bilu"
+    _check_against_golden(case, b, g, "fullsize BILU vs oracle", second_stage=1)
+
+
 def test_fullsize_bilu_second_stage_bit_exact(big):
     """Block ILU(0) second stage at full size, in the launch configuration the
     benchmark times with --second-stage bilu (363 forward and 363 backward
