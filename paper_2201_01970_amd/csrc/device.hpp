@@ -135,11 +135,15 @@ void launch_gcr_orth(int64_t n, const double* part, const double* scal, T* w2, c
 // x = alpha1 z1 + alpha2 x, alpha2 = (r1,w2)/(w2,w2) from part2
 template <typename T>
 void launch_gcr_finish(int64_t n, const double* part2, const double* scal, T* x, const T* z1, hipStream_t s);
-// Gauss-Jordan step k on the row-major n x n matrix a (col2: 2n scratch
-// doubles holding column k of the current matrix in alternating halves, so
-// steps 0..n-1 must run in order on one stream; piv[k] = pivot row; *bad = 1
-// when column k has no nonzero pivot)
-void launch_gj_step(int n, int k, double* a, int32_t* piv, double* col2, int32_t* bad, hipStream_t s);
+// Gauss-Jordan elimination with partial pivoting of the row-major n x n
+// matrix a in place, by panels of 64 columns (work: gj_workspace_doubles(n)
+// doubles, iwork: gj_workspace_ints(n) ints).  Afterwards a holds the inverse
+// of the row-interchanged matrix; piv[k] = the row interchanged with row k at
+// step k; *bad is set to 1 when a column has no nonzero pivot (*bad is not
+// cleared here).
+int64_t gj_workspace_doubles(int n);
+int64_t gj_workspace_ints(int n);
+void launch_gj_inverse(int n, double* a, double* work, int32_t* iwork, int32_t* piv, int32_t* bad, hipStream_t s);
 // dst[i][j] = src[i][cols[j]] (n x n, row-major)
 void launch_permute_cols(int n, const double* src, const int32_t* cols, double* dst, hipStream_t s);
 // x = Ainv b (Ainv n x n FP64 row-major; b, x in T)

@@ -203,97 +203,276 @@ CPR_GCR_INST(float)
 
 // ------------------------------------------------ coarsest level: dense inverse
 // In-place Gauss-Jordan elimination with partial pivoting on the row-major
-// n x n matrix a, step k.  Column k of the matrix before step k is kept
-// contiguous in cur[0..n) (written by the previous step, so the pivot search
-// reads it without striding through a).  Pivot search, row swap and the
-// scaling of the pivot row run in one workgroup; the elimination of the other
-// rows in a second kernel, which also leaves column k+1 in nxt.  After step k,
-// row k holds (row k)/pivot with entry k = 1/pivot, and every other row i has
-// had m_i (its old entry k) times the new row k subtracted, entry k becoming
-// -m_i/pivot.
-constexpr int kGjBlock = 1024;
+// n x n matrix a.  Step k: p = the row >= k of largest |a[p][k]| (ties to the
+// smaller row), rows k and p interchanged, row k divided by the pivot with
+// entry k becoming 1/pivot, and every other row i losing m_i (its entry k)
+// times the new row k, its entry k becoming -m_i/pivot.  A step changes
+// column j using only columns j and k, so the steps of a panel of kb columns
+// [k0, k0 + kb) run on a copy of those columns alone (every row), and their
+// effect on every other column j is, with the panel's row interchanges
+// applied first,
+//   a[i][j] = (k0 <= i < k0 + kb ? 0 : a[i][j]) + sum_t X[i][t] Y[t][j],
+// X the eliminated panel and Y rows k0..k0+kb-1 before the update: one
+// rank-kb update of the matrix per panel instead of a full pass per column.
+constexpr int kGjPanel = 64;                 // columns per panel, one per lane
+constexpr int kGjRows = 64;                  // rows per workgroup of a column step
+constexpr int kGjThreads = 1024;             // 16 wavefronts of four rows each
+constexpr int kGjWaves = kGjThreads / 64;
+constexpr int kGjSwapThreads = 64;
+constexpr int kGjTile = 64;                  // update tile: 64 x 64 entries, 256 threads
 
-__global__ __launch_bounds__(kBlock) void k_gj_column(int n, const double* __restrict__ a, double* __restrict__ col) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) col[i] = a[(int64_t)i * n];
+// (v, i) ranks above (bv, bi): larger magnitude, ties to the smaller row
+__device__ __forceinline__ bool gj_better(double v, int i, double bv, int bi) {
+  return v > bv || (v == bv && i < bi);
 }
 
-__global__ __launch_bounds__(kGjBlock) void k_gj_pivot(int n, int k, double* __restrict__ a, int32_t* __restrict__ piv,
-                                                       double* __restrict__ cur, double* __restrict__ nxt,
-                                                       int32_t* __restrict__ bad) {
-  __shared__ double sv[kGjBlock];
-  __shared__ int si[kGjBlock];
-  double best = -1.0;
+// The workgroup's pivot candidate from the one held by lane `owner` of every
+// wavefront, stored at cv[blockIdx.x], ci[blockIdx.x].
+__device__ void gj_block_candidate(double v, int i, int owner, double* cv, int32_t* ci) {
+  __shared__ double sv[kGjWaves];
+  __shared__ int si[kGjWaves];
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == owner) {
+    sv[wave] = v;
+    si[wave] = i;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bv = sv[0];
+    int bi = si[0];
+    for (int w = 1; w < kGjWaves; ++w)
+      if (gj_better(sv[w], si[w], bv, bi)) {
+        bv = sv[w];
+        bi = si[w];
+      }
+    cv[blockIdx.x] = bv;
+    ci[blockIdx.x] = bi;
+  }
+}
+
+// pan (n x kGjPanel, row-major) = columns k0..k0+kb-1 of a, zero beyond kb;
+// the candidates for the pivot of column k0.
+__global__ __launch_bounds__(kGjThreads) void k_gj_panel_load(int n, int k0, int kb, const double* __restrict__ a,
+                                                              double* __restrict__ pan, double* __restrict__ cv,
+                                                              int32_t* __restrict__ ci) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double bv = -1.0;
   int bi = n;
-  for (int i = k + (int)threadIdx.x; i < n; i += kGjBlock) {
-    const double v = fabs(cur[i]);
-    if (v > best) {  // rows visited in ascending order: ties keep the smallest index
-      best = v;
+  for (int m = 0; m < kGjRows / kGjWaves; ++m) {
+    const int i = blockIdx.x * kGjRows + wave + kGjWaves * m;
+    if (i >= n) break;
+    const double v = lane < kb ? a[(int64_t)i * n + k0 + lane] : 0.0;
+    pan[(int64_t)i * kGjPanel + lane] = v;
+    if (lane == 0 && i >= k0 && fabs(v) > bv) {
+      bv = fabs(v);
       bi = i;
     }
   }
-  sv[threadIdx.x] = best;
-  si[threadIdx.x] = bi;
-  __syncthreads();
-  for (int w = kGjBlock / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      const double ov = sv[threadIdx.x + w];
-      const int oi = si[threadIdx.x + w];
-      if (ov > sv[threadIdx.x] || (ov == sv[threadIdx.x] && oi < si[threadIdx.x])) {
-        sv[threadIdx.x] = ov;
-        si[threadIdx.x] = oi;
+  gj_block_candidate(bv, bi, 0, cv, ci);
+}
+
+// Step k = k0 + t on the panel: src -> dst.  Every workgroup reduces the
+// candidates of the previous launch to the same pivot row, and leaves its
+// candidate for column t + 1 (rows > k).  Lane j holds panel column j; the
+// wavefront of a row is uniform, so the shuffles see every lane.
+__global__ __launch_bounds__(kGjThreads) void k_gj_panel_step(int n, int k0, int kb, int t, int nwg,
+                                                              const double* __restrict__ src, double* __restrict__ dst,
+                                                              const double* __restrict__ cv_in,
+                                                              const int32_t* __restrict__ ci_in,
+                                                              double* __restrict__ cv_out, int32_t* __restrict__ ci_out,
+                                                              int32_t* __restrict__ piv, int32_t* __restrict__ bad) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int k = k0 + t;
+  constexpr int kM = kGjRows / kGjWaves;
+  double rv[kM];  // this workgroup's rows, requested before the pivot is known
+#pragma unroll
+  for (int m = 0; m < kM; ++m) {
+    const int i = blockIdx.x * kGjRows + wave + kGjWaves * m;
+    rv[m] = i < n ? src[(int64_t)i * kGjPanel + lane] : 0.0;
+  }
+  double bv = -1.0;
+  int bi = n;
+  for (int w = lane; w < nwg; w += 64)
+    if (gj_better(cv_in[w], ci_in[w], bv, bi)) {
+      bv = cv_in[w];
+      bi = ci_in[w];
+    }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(bv, off, 64);
+    const int oi = __shfl_xor(bi, off, 64);
+    if (gj_better(ov, oi, bv, bi)) {
+      bv = ov;
+      bi = oi;
+    }
+  }
+  const bool ok = bi < n && bv > 0.0;
+  const int p = ok ? bi : k;
+  const double rk = src[(int64_t)k * kGjPanel + lane];
+  const double rp = p == k ? rk : src[(int64_t)p * kGjPanel + lane];
+  const double pv = ok ? __shfl(rp, t, 64) : 1.0;
+  const double sp = (lane == t ? 1.0 : rp) / pv;  // the new row k
+  double cbv = -1.0;
+  int cbi = n;
+#pragma unroll
+  for (int m = 0; m < kM; ++m) {
+    const int i = blockIdx.x * kGjRows + wave + kGjWaves * m;
+    if (i < n) {
+      double out;
+      if (i == k) {
+        out = sp;
+      } else {
+        const double v = i == p ? rk : rv[m];
+        const double f = __shfl(v, t, 64);
+        const double prod = f * sp;
+        out = (lane == t ? 0.0 : v) - prod;
+      }
+      dst[(int64_t)i * kGjPanel + lane] = out;
+      if (lane == t + 1 && i > k && fabs(out) > cbv) {
+        cbv = fabs(out);
+        cbi = i;
       }
     }
-    __syncthreads();
   }
-  const int p = si[0];
-  const bool ok = p < n && sv[0] > 0.0;
-  if (p < n && p != k) {
-    for (int j = threadIdx.x; j < n; j += kGjBlock) {
-      const double t = a[(int64_t)k * n + j];
-      a[(int64_t)k * n + j] = a[(int64_t)p * n + j];
-      a[(int64_t)p * n + j] = t;
-    }
-    if (threadIdx.x == 0) {
-      const double t = cur[k];
-      cur[k] = cur[p];
-      cur[p] = t;
-    }
-  }
-  __syncthreads();
-  const double pv = ok ? a[(int64_t)k * n + k] : 1.0;
-  __syncthreads();
-  for (int j = threadIdx.x; j < n; j += kGjBlock) {
-    const double v = j == k ? 1.0 : a[(int64_t)k * n + j];
-    const double r = v / pv;
-    a[(int64_t)k * n + j] = r;
-    if (j == k + 1) nxt[k] = r;
-  }
-  if (threadIdx.x == 0) {
-    piv[k] = ok ? p : k;
+  if (t + 1 < kb) gj_block_candidate(cbv, cbi, t + 1, cv_out, ci_out);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    piv[k] = p;
     if (!ok) bad[0] = 1;
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_gj_eliminate(int n, int k, double* __restrict__ a,
-                                                         const double* __restrict__ cur, double* __restrict__ nxt) {
-  const int i = blockIdx.x;
-  if (i == k) return;
-  const double f = cur[i];
-  double* row = a + (int64_t)i * n;
-  // a zero multiplier leaves the row as it is (the coarsest Galerkin matrix
-  // is sparse, so most rows of the early steps have nothing to eliminate)
-  if (f == 0.0) {
-    if (threadIdx.x == 0 && k + 1 < n) nxt[i] = row[k + 1];
+// The panel's row interchanges, in step order, on every column outside the
+// panel (one thread per column): rows k0..k0+kb-1 leave their values in y
+// (row t of y is row k0 + t) and hold zero.  The interchanges move at most
+// 2 kb rows; the first thread lists them (pos: row, org: the row its value
+// comes from).
+__global__ __launch_bounds__(kGjSwapThreads) void k_gj_panel_swap(int n, int k0, int kb, double* __restrict__ a,
+                                                                  const int32_t* __restrict__ piv,
+                                                                  double* __restrict__ y) {
+  __shared__ int pos[2 * kGjPanel], org[2 * kGjPanel];
+  __shared__ int cnt;
+  __shared__ double vals[2 * kGjPanel][kGjSwapThreads];
+  if (threadIdx.x == 0) {
+    int c = kb;
+    for (int t = 0; t < kb; ++t) {
+      pos[t] = k0 + t;
+      org[t] = k0 + t;
+    }
+    for (int t = 0; t < kb; ++t) {
+      const int p = piv[k0 + t];
+      if (p == k0 + t) continue;
+      int m = -1;
+      for (int q = t + 1; q < c; ++q)
+        if (pos[q] == p) {
+          m = q;
+          break;
+        }
+      if (m < 0) {
+        m = c++;
+        pos[m] = p;
+        org[m] = p;
+      }
+      const int o = org[t];
+      org[t] = org[m];
+      org[m] = o;
+    }
+    cnt = c;
+  }
+  __syncthreads();
+  const int j = blockIdx.x * kGjSwapThreads + threadIdx.x;
+  if (j >= n || (j >= k0 && j < k0 + kb)) return;
+  const int c = cnt;
+  for (int m = 0; m < c; ++m) vals[m][threadIdx.x] = a[(int64_t)org[m] * n + j];
+  for (int m = 0; m < c; ++m) {
+    const double v = vals[m][threadIdx.x];
+    if (m < kb) {
+      y[(int64_t)m * n + j] = v;
+      a[(int64_t)pos[m] * n + j] = 0.0;
+    } else {
+      a[(int64_t)pos[m] * n + j] = v;
+    }
+  }
+}
+
+// a[i][j] += sum_t x[i][t] y[t][j] outside the panel's columns, which take x.
+// 64 x 64 tiles; thread (ty, tx) owns rows 4 ty + r and columns tx + 16 c.
+__global__ __launch_bounds__(256) void k_gj_panel_update(int n, int k0, int kb, double* __restrict__ a,
+                                                         const double* __restrict__ x, const double* __restrict__ y) {
+  __shared__ double xs[kGjTile][kGjPanel + 1];
+  __shared__ double ys[kGjPanel][kGjTile];
+  const int i0 = blockIdx.y * kGjTile, j0 = blockIdx.x * kGjTile;
+  if (j0 == k0) {  // panels start on tile boundaries
+    for (int e = threadIdx.x; e < kGjTile * kGjPanel; e += 256) {
+      const int r = e / kGjPanel, t = e % kGjPanel;
+      if (i0 + r < n && t < kb) a[(int64_t)(i0 + r) * n + k0 + t] = x[(int64_t)(i0 + r) * kGjPanel + t];
+    }
     return;
   }
-  const double* rk = a + (int64_t)k * n;
-  for (int j = threadIdx.x; j < n; j += kBlock) {
-    const double v = j == k ? 0.0 : row[j];
-    const double prod = f * rk[j];
-    const double r = v - prod;
-    row[j] = r;
-    if (j == k + 1) nxt[i] = r;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = i0 + 4 * ty + r, j = j0 + tx + 16 * c;
+      acc[r][c] = (i < n && j < n) ? a[(int64_t)i * n + j] : 0.0;
+    }
+  for (int e = threadIdx.x; e < kGjTile * kGjPanel; e += 256) {
+    const int r = e / kGjPanel, t = e % kGjPanel;
+    xs[r][t] = i0 + r < n ? x[(int64_t)(i0 + r) * kGjPanel + t] : 0.0;
+  }
+  for (int e = threadIdx.x; e < kGjPanel * kGjTile; e += 256) {
+    const int t = e / kGjTile, c = e % kGjTile;
+    ys[t][c] = (t < kb && j0 + c < n) ? y[(int64_t)t * n + j0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int t = 0; t < kb; ++t) {
+    double xr[4], yc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) xr[r] = xs[4 * ty + r][t];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) yc[c] = ys[t][tx + 16 * c];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] = fma(xr[r], yc[c], acc[r][c]);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = i0 + 4 * ty + r, j = j0 + tx + 16 * c;
+      if (i < n && j < n) a[(int64_t)i * n + j] = acc[r][c];
+    }
+}
+
+int64_t gj_workspace_doubles(int n) {
+  const int64_t nwg = div_up(n, kGjRows);
+  return 2 * (int64_t)n * kGjPanel + (int64_t)kGjPanel * n + 2 * nwg;
+}
+
+int64_t gj_workspace_ints(int n) { return 2 * (int64_t)div_up(n, kGjRows); }
+
+void launch_gj_inverse(int n, double* a, double* work, int32_t* iwork, int32_t* piv, int32_t* bad, hipStream_t s) {
+  const int nwg = div_up(n, kGjRows);
+  double* pan[2] = {work, work + (int64_t)n * kGjPanel};
+  double* y = work + 2 * (int64_t)n * kGjPanel;
+  double* cv[2] = {y + (int64_t)kGjPanel * n, y + (int64_t)kGjPanel * n + nwg};
+  int32_t* ci[2] = {iwork, iwork + nwg};
+  const int tiles = div_up(n, kGjTile);
+  for (int k0 = 0; k0 < n; k0 += kGjPanel) {
+    const int kb = std::min(kGjPanel, n - k0);
+    hipLaunchKernelGGL(k_gj_panel_load, dim3(nwg), dim3(kGjThreads), 0, s, n, k0, kb, a, pan[0], cv[0], ci[0]);
+    CPR_LAUNCH_CHECK();
+    for (int t = 0; t < kb; ++t) {
+      hipLaunchKernelGGL(k_gj_panel_step, dim3(nwg), dim3(kGjThreads), 0, s, n, k0, kb, t, nwg, pan[t & 1],
+                         pan[(t + 1) & 1], cv[t & 1], ci[t & 1], cv[(t + 1) & 1], ci[(t + 1) & 1], piv, bad);
+      CPR_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_gj_panel_swap, dim3(div_up(n, kGjSwapThreads)), dim3(kGjSwapThreads), 0, s, n, k0, kb, a,
+                       piv, y);
+    CPR_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_gj_panel_update, dim3(tiles, tiles), dim3(256), 0, s, n, k0, kb, a, pan[kb & 1], y);
+    CPR_LAUNCH_CHECK();
   }
 }
 
@@ -302,19 +481,6 @@ __global__ __launch_bounds__(kBlock) void k_permute_cols(int n, const double* __
                                                          const int32_t* __restrict__ cols, double* __restrict__ dst) {
   const int i = blockIdx.x;
   for (int j = threadIdx.x; j < n; j += kBlock) dst[(int64_t)i * n + j] = src[(int64_t)i * n + cols[j]];
-}
-
-void launch_gj_step(int n, int k, double* a, int32_t* piv, double* col2, int32_t* bad, hipStream_t s) {
-  double* cur = col2 + (int64_t)(k & 1) * n;
-  double* nxt = col2 + (int64_t)((k + 1) & 1) * n;
-  if (k == 0) {
-    hipLaunchKernelGGL(k_gj_column, dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, a, cur);
-    CPR_LAUNCH_CHECK();
-  }
-  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kGjBlock), 0, s, n, k, a, piv, cur, nxt, bad);
-  CPR_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_gj_eliminate, dim3(n), dim3(kBlock), 0, s, n, k, a, cur, nxt);
-  CPR_LAUNCH_CHECK();
 }
 
 void launch_permute_cols(int n, const double* src, const int32_t* cols, double* dst, hipStream_t s) {

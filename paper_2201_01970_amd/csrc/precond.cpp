@@ -969,11 +969,12 @@ class Precond final : public PrecondBase {
     const int n = nL_;
     Arena work;  // released when SETUP returns
     double* a = work.upload(dense);
-    double* col2 = work.alloc<double>(2 * static_cast<int64_t>(n));
+    double* gj = work.alloc<double>(gj_workspace_doubles(n));
+    int32_t* igj = work.alloc<int32_t>(gj_workspace_ints(n));
     int32_t* piv = work.alloc<int32_t>(n);
     int32_t* bad = work.alloc<int32_t>(1);
     launch_fill<int32_t>(1, 0, bad, s);
-    for (int k = 0; k < n; ++k) launch_gj_step(n, k, a, piv, col2, bad, s);
+    launch_gj_inverse(n, a, gj, igj, piv, bad, s);
     std::vector<int32_t> hpiv(n);
     int32_t hbad = 0;
     HIPCHK(hipMemcpyAsync(hpiv.data(), piv, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));

@@ -223,3 +223,63 @@ def test_oversized_coarsest_is_refused(solver):
     case = bo.case_spe10_like(seed=1110, shape=(30, 40, 20))  # 23400 pressure rows
     with pytest.raises(CprError, match="dense direct solve"):
         _solver(case, coarse_max=10 ** 6, coarse_solver=solver)
+
+
+def _weak_pressure_diagonal_case(scale):
+    """The 12x10x4 grid with the pressure entry of every diagonal block
+    multiplied by `scale`: for scale 1e-3 the pressure matrix's largest entry
+    of a column is off the diagonal, so partial pivoting interchanges rows at
+    nearly every step (471 of 480 in LAPACK's factorisation)."""
+    case = bo.case_small(seed=7, shape=(12, 10, 4))
+    v = case.vals.copy()
+    for i in range(case.n_b):
+        lo, hi = case.row_ptr[i], case.row_ptr[i + 1]
+        v[lo + int(np.nonzero(case.col[lo:hi] == i)[0][0]), 0, 0] *= scale
+    case.vals = v
+    return case
+
+
+def test_inverse_with_row_interchanges():
+    """A single-level hierarchy whose 480-row pressure matrix needs row
+    interchanges at nearly every elimination step (7 full column panels and
+    a ragged one): the V-cycle, A_P^{-1} r, within 100 eps cond(A_P) of
+    LAPACK's solve, and the CPR apply within 1e-10 of the oracle's."""
+    import scipy.linalg as sl
+
+    case = _weak_pressure_diagonal_case(1e-3)
+    A = cpr.Bsr.from_case(case)
+    B = cpr.setup(A, amg.AmgParams(coarse_max=10 ** 6))
+    assert B.amg.n_levels == 1
+    Ad = B.amg.levels[0].A.to_dense()
+    _, piv = sl.lu_factor(Ad)
+    assert (piv != np.arange(Ad.shape[0])).sum() > 400
+    S = _solver(case, coarse_max=10 ** 6, coarse_solver=1)
+    rng = np.random.default_rng(31)
+    r = rng.standard_normal(A.n_b)
+    got = S.vcycle(_dev(r)).cpu().numpy()
+    want = np.linalg.solve(Ad, r)
+    bound = 100 * np.finfo(np.float64).eps * np.linalg.cond(Ad)
+    d = np.linalg.norm(got - want) / np.linalg.norm(want)
+    v = rng.standard_normal(case.ndof)
+    wa = B.apply(v)
+    da = np.linalg.norm(S.precond(_dev(v)).cpu().numpy() - wa) / np.linalg.norm(wa)
+    print(f"[interchanges] cond {np.linalg.cond(Ad):.2e}: vcycle diff {d:.2e} (bound {bound:.2e}), apply {da:.2e}",
+          flush=True)
+    S.close()
+    assert d <= bound
+    assert da <= 1e-10
+
+
+def test_singular_coarsest_is_refused():
+    """A pressure matrix with a zero column (the pressure entries of one cell's
+    column set to zero; its 3x3 diagonal block stays invertible) has no pivot
+    in that column: SETUP fails with CPR_ERR_SINGULAR_COARSE."""
+    from paper_2201_01970_amd import CprError
+
+    case = bo.case_small(seed=7, shape=(12, 10, 4))
+    v = case.vals.copy()
+    j = 137
+    v[case.col == j, 0, 0] = 0.0
+    case.vals = v
+    with pytest.raises(CprError, match="singular"):
+        _solver(case, coarse_max=10 ** 6, coarse_solver=1)
