@@ -11,6 +11,7 @@
 #include <memory>
 #include <mutex>
 #include <queue>
+#include <set>
 #include <thread>
 #include <utility>
 
@@ -521,22 +522,52 @@ bool rs_interpolation(const HostCsr& A, const std::vector<uint8_t>& mask, uint8_
   return ok;
 }
 
+// Rows split into up to 16 contiguous blocks: each block counts its entries
+// per column, a column's blocks then take consecutive ranges of the column
+// in block order, and each block writes its rows in ascending order, so every
+// column of the result lists its rows in ascending order whatever the thread
+// count (as a sequential transpose does).
 HostCsr transpose(const HostCsr& A) {
   HostCsr T;
-  T.n_rows = A.n_cols;
-  T.n_cols = A.n_rows;
-  T.ptr.assign(A.n_cols + 1, 0);
-  for (int32_t c : A.col) T.ptr[c + 1]++;
-  for (int32_t i = 0; i < A.n_cols; ++i) T.ptr[i + 1] += T.ptr[i];
+  const int32_t n = A.n_rows, m = A.n_cols;
+  T.n_rows = m;
+  T.n_cols = n;
+  T.ptr.assign(static_cast<size_t>(m) + 1, 0);
   T.col.resize(A.col.size());
   T.val.resize(A.val.size());
-  std::vector<int32_t> fill(T.ptr.begin(), T.ptr.end() - 1);
-  for (int32_t i = 0; i < A.n_rows; ++i)
-    for (int32_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
-      const int32_t w = fill[A.col[p]]++;
-      T.col[w] = i;
-      T.val[w] = A.val[p];
+  const int nb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(setup_threads(), A.nnz() / 262144)));
+  auto row0 = [&](int b) { return static_cast<int32_t>(static_cast<int64_t>(n) * b / nb); };
+  std::vector<std::vector<int32_t>> cnt(nb);
+  parallel_chunks(nb, [&](int b, int) {
+    std::vector<int32_t>& c = cnt[b];
+    c.assign(static_cast<size_t>(m), 0);
+    for (int32_t p = A.ptr[row0(b)]; p < A.ptr[row0(b + 1)]; ++p) c[A.col[p]]++;
+  });
+  // cnt[b][j] becomes block b's first slot within column j
+  const int ncb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(64, m / 4096)));
+  parallel_chunks(ncb, [&](int cb, int) {
+    const int32_t j1 = static_cast<int32_t>(static_cast<int64_t>(m) * (cb + 1) / ncb);
+    for (int32_t j = static_cast<int32_t>(static_cast<int64_t>(m) * cb / ncb); j < j1; ++j) {
+      int32_t sum = 0;
+      for (int b = 0; b < nb; ++b) {
+        const int32_t c = cnt[b][j];
+        cnt[b][j] = sum;
+        sum += c;
+      }
+      T.ptr[j + 1] = sum;
     }
+  });
+  for (int32_t j = 0; j < m; ++j) T.ptr[j + 1] += T.ptr[j];
+  parallel_chunks(nb, [&](int b, int) {
+    std::vector<int32_t>& c = cnt[b];
+    for (int32_t i = row0(b); i < row0(b + 1); ++i)
+      for (int32_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+        const int32_t j = A.col[p];
+        const int32_t w = T.ptr[j] + c[j]++;
+        T.col[w] = i;
+        T.val[w] = A.val[p];
+      }
+  });
   return T;
 }
 
@@ -786,13 +817,19 @@ int32_t bilu0_factor(int32_t n, const int32_t* rp, const int32_t* col, const std
 int32_t pairwise_matching(const HostCsr& A, double beta, std::vector<int32_t>& agg) {
   const int32_t n = A.n_rows;
   const HostCsr T = transpose(A);
-  // symmetric part: merge row i of A (a_ij) and of A^T (a_ji), columns ascending
-  std::vector<int64_t> sp(n + 1, 0);
-  std::vector<int32_t> sc;
-  std::vector<double> sv;
-  sc.reserve(A.col.size() * 2);
-  sv.reserve(A.col.size() * 2);
-  for (int32_t i = 0; i < n; ++i) {
+  // Strong set of row i: with s_ij = a_ij/2 + a_ji/2 over the merged
+  // columns j != i of row i of A and of A^T (ascending), the j with
+  // s_ij < -beta max_k(-s_ik), when that maximum is positive.  Rows are
+  // independent: a counting pass, then a filling pass, over row chunks.
+  std::vector<int64_t> Sp(static_cast<size_t>(n) + 1, 0);
+  std::vector<int32_t> Sc;
+  std::vector<double> Sv;  // s_ij of each strong entry
+  RowChunks rc(n);
+  // mc, mv: the chunk's own scratch for the merged row
+  auto strong_row = [&](int32_t i, std::vector<int32_t>& mc, std::vector<double>& mv, int32_t* out_c,
+                        double* out_v) -> int64_t {
+    mc.clear();
+    mv.clear();
     int32_t p = A.ptr[i], q = T.ptr[i];
     const int32_t pe = A.ptr[i + 1], qe = T.ptr[i + 1];
     while (p < pe || q < qe) {
@@ -812,44 +849,77 @@ int32_t pairwise_matching(const HostCsr& A, double beta, std::vector<int32_t>& a
       double acc = 0.0;
       if (has_lo) acc = acc + h_lo;
       if (has_hi) acc = acc + h_hi;
-      sc.push_back(j);
-      sv.push_back(acc);
+      mc.push_back(j);
+      mv.push_back(acc);
     }
-    sp[i + 1] = static_cast<int64_t>(sc.size());
-  }
-  // strong sets
-  std::vector<int64_t> Sp(n + 1, 0);
-  std::vector<int32_t> Sc;
-  std::vector<double> Sv;  // s_ij of each strong entry
-  for (int32_t i = 0; i < n; ++i) {
     double top = 0.0;
-    bool any = false;
-    for (int64_t e = sp[i]; e < sp[i + 1]; ++e) {
-      const double v = -sv[e];
-      top = any ? std::max(top, v) : v;
-      any = true;
-    }
-    if (any && top > 0.0)
-      for (int64_t e = sp[i]; e < sp[i + 1]; ++e)
-        if (sv[e] < -beta * top) {
-          Sc.push_back(sc[e]);
-          Sv.push_back(sv[e]);
+    for (size_t e = 0; e < mv.size(); ++e) top = e == 0 ? -mv[e] : std::max(top, -mv[e]);
+    int64_t c = 0;
+    if (!mv.empty() && top > 0.0)
+      for (size_t e = 0; e < mv.size(); ++e)
+        if (mv[e] < -beta * top) {
+          if (out_c) {
+            out_c[c] = mc[e];
+            out_v[c] = mv[e];
+          }
+          ++c;
         }
-    Sp[i + 1] = static_cast<int64_t>(Sc.size());
-  }
+    return c;
+  };
+  parallel_chunks(rc.n_chunks, [&](int ch, int) {
+    std::vector<int32_t> mc;
+    std::vector<double> mv;
+    for (int32_t i = rc.begin(ch); i < rc.end(ch); ++i) Sp[i + 1] = strong_row(i, mc, mv, nullptr, nullptr);
+  });
+  for (int32_t i = 0; i < n; ++i) Sp[i + 1] += Sp[i];
+  Sc.resize(static_cast<size_t>(Sp[n]));
+  Sv.resize(static_cast<size_t>(Sp[n]));
+  parallel_chunks(rc.n_chunks, [&](int ch, int) {
+    std::vector<int32_t> mc;
+    std::vector<double> mv;
+    for (int32_t i = rc.begin(ch); i < rc.end(ch); ++i) strong_row(i, mc, mv, Sc.data() + Sp[i], Sv.data() + Sp[i]);
+  });
   std::vector<int64_t> m(n, 0);
   for (int32_t i = 0; i < n; ++i)
     for (int64_t e = Sp[i]; e < Sp[i + 1]; ++e) m[Sc[e]] += 1;
-  using Entry = std::pair<int64_t, int32_t>;
-  std::priority_queue<Entry, std::vector<Entry>, std::greater<Entry>> heap;
-  for (int32_t i = 0; i < n; ++i) heap.push({m[i], i});
+  // The unaggregated nodes in ascending (m_i, i).  m_i only falls, so one
+  // IndexSet per value of m up to kCap holds them, with a pointer to the
+  // lowest non-empty set; the rarer nodes of larger m wait in an ordered set
+  // and move into the sets once m_i reaches kCap.
+  constexpr int64_t kCap = 63;
+  int64_t max_m = 0;
+  for (int32_t i = 0; i < n; ++i) max_m = std::max(max_m, m[i]);
+  const int64_t n_sets = std::min(max_m, kCap) + 1;
+  std::vector<IndexSet> bucket;
+  bucket.reserve(static_cast<size_t>(n_sets));
+  for (int64_t v = 0; v < n_sets; ++v) bucket.emplace_back(n);
+  std::set<std::pair<int64_t, int32_t>> high;
+  for (int32_t i = 0; i < n; ++i) {
+    if (m[i] <= kCap)
+      bucket[m[i]].insert(i);
+    else
+      high.insert({m[i], i});
+  }
+  auto take_out = [&](int32_t k) {
+    if (m[k] <= kCap)
+      bucket[m[k]].erase(k);
+    else
+      high.erase({m[k], k});
+  };
+  int64_t low = 0;
   agg.assign(n, -1);
   int32_t n_agg = 0;
-  while (!heap.empty()) {
-    const Entry top = heap.top();
-    heap.pop();
-    const int32_t i = top.second;
-    if (agg[i] >= 0 || top.first != m[i]) continue;
+  while (true) {
+    while (low < n_sets && bucket[low].empty()) ++low;
+    int32_t i;
+    if (low < n_sets) {
+      i = bucket[low].first();
+    } else if (!high.empty()) {
+      i = high.begin()->second;
+    } else {
+      break;
+    }
+    take_out(i);
     int32_t best = -1;
     double best_v = 0.0;
     for (int64_t e = Sp[i]; e < Sp[i + 1]; ++e) {
@@ -860,14 +930,25 @@ int32_t pairwise_matching(const HostCsr& A, double beta, std::vector<int32_t>& a
         best_v = Sv[e];
       }
     }
+    if (best >= 0) take_out(best);
     const int32_t members[2] = {i, best};
     const int nm = best < 0 ? 1 : 2;
     for (int t = 0; t < nm; ++t) agg[members[t]] = n_agg;
     for (int t = 0; t < nm; ++t)
       for (int64_t e = Sp[members[t]]; e < Sp[members[t] + 1]; ++e) {
         const int32_t k = Sc[e];
+        if (agg[k] >= 0) {
+          m[k] -= 1;
+          continue;
+        }
+        take_out(k);
         m[k] -= 1;
-        if (agg[k] < 0) heap.push({m[k], k});
+        if (m[k] <= kCap) {
+          bucket[m[k]].insert(k);
+          low = std::min(low, m[k]);
+        } else {
+          high.insert({m[k], k});
+        }
       }
     ++n_agg;
   }
