@@ -145,6 +145,51 @@ struct RowChunks {
 
 void parallel_for(int n_chunks, const std::function<void(int, int)>& f) { parallel_chunks(n_chunks, f); }
 
+namespace {
+// Transpose of an n x m pattern (ptr, col) in blocks of rows: each block
+// counts its entries per column, a column's blocks then take consecutive
+// ranges of the column in block order, and each block writes its rows in
+// ascending order, so every column of the result lists its rows in
+// ascending order whatever the thread count (as a sequential transpose
+// does).  tptr (m + 1 entries, zero on entry) receives the row pointers;
+// put(w, i, p) stores entry p (row i) of the input at position w.
+template <typename Put>
+void transpose_blocks(int32_t n, int32_t m, int64_t nnz, const int32_t* ptr, const int32_t* col, int32_t* tptr,
+                      Put&& put) {
+  const int nb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(setup_threads(), nnz / 262144)));
+  auto row0 = [&](int b) { return static_cast<int32_t>(static_cast<int64_t>(n) * b / nb); };
+  std::vector<std::vector<int32_t>> cnt(nb);
+  parallel_chunks(nb, [&](int b, int) {
+    std::vector<int32_t>& c = cnt[b];
+    c.assign(static_cast<size_t>(m), 0);
+    for (int32_t p = ptr[row0(b)]; p < ptr[row0(b + 1)]; ++p) c[col[p]]++;
+  });
+  // cnt[b][j] becomes block b's first slot within column j
+  const int ncb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(64, m / 4096)));
+  parallel_chunks(ncb, [&](int cb, int) {
+    const int32_t j1 = static_cast<int32_t>(static_cast<int64_t>(m) * (cb + 1) / ncb);
+    for (int32_t j = static_cast<int32_t>(static_cast<int64_t>(m) * cb / ncb); j < j1; ++j) {
+      int32_t sum = 0;
+      for (int b = 0; b < nb; ++b) {
+        const int32_t c = cnt[b][j];
+        cnt[b][j] = sum;
+        sum += c;
+      }
+      tptr[j + 1] = sum;
+    }
+  });
+  for (int32_t j = 0; j < m; ++j) tptr[j + 1] += tptr[j];
+  parallel_chunks(nb, [&](int b, int) {
+    std::vector<int32_t>& c = cnt[b];
+    for (int32_t i = row0(b); i < row0(b + 1); ++i)
+      for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p) {
+        const int32_t j = col[p];
+        put(static_cast<int64_t>(tptr[j]) + c[j]++, i, p);
+      }
+  });
+}
+}  // namespace
+
 Pattern pattern_from_mask(const HostCsr& A, const std::vector<uint8_t>& mask, uint8_t bit) {
   Pattern S;
   const int32_t n = A.n_rows;
@@ -173,13 +218,10 @@ Pattern pattern_from_mask(const HostCsr& A, const std::vector<uint8_t>& mask, ui
 Pattern transpose_pattern(const Pattern& S) {
   Pattern T;
   T.n = S.n;
-  T.ptr.assign(S.n + 1, 0);
-  for (int32_t c : S.col) T.ptr[c + 1]++;
-  for (int32_t i = 0; i < S.n; ++i) T.ptr[i + 1] += T.ptr[i];
+  T.ptr.assign(static_cast<size_t>(S.n) + 1, 0);
   T.col.resize(S.col.size());
-  std::vector<int32_t> fill(T.ptr.begin(), T.ptr.end() - 1);
-  for (int32_t i = 0; i < S.n; ++i)  // rows ascending -> each T row ascending
-    for (int32_t p = S.ptr[i]; p < S.ptr[i + 1]; ++p) T.col[fill[S.col[p]]++] = i;
+  transpose_blocks(S.n, S.n, static_cast<int64_t>(S.col.size()), S.ptr.data(), S.col.data(), T.ptr.data(),
+                   [&](int64_t w, int32_t i, int32_t) { T.col[w] = i; });
   return T;
 }
 
@@ -522,52 +564,18 @@ bool rs_interpolation(const HostCsr& A, const std::vector<uint8_t>& mask, uint8_
   return ok;
 }
 
-// Rows split into up to 16 contiguous blocks: each block counts its entries
-// per column, a column's blocks then take consecutive ranges of the column
-// in block order, and each block writes its rows in ascending order, so every
-// column of the result lists its rows in ascending order whatever the thread
-// count (as a sequential transpose does).
 HostCsr transpose(const HostCsr& A) {
   HostCsr T;
-  const int32_t n = A.n_rows, m = A.n_cols;
-  T.n_rows = m;
-  T.n_cols = n;
-  T.ptr.assign(static_cast<size_t>(m) + 1, 0);
+  T.n_rows = A.n_cols;
+  T.n_cols = A.n_rows;
+  T.ptr.assign(static_cast<size_t>(A.n_cols) + 1, 0);
   T.col.resize(A.col.size());
   T.val.resize(A.val.size());
-  const int nb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(setup_threads(), A.nnz() / 262144)));
-  auto row0 = [&](int b) { return static_cast<int32_t>(static_cast<int64_t>(n) * b / nb); };
-  std::vector<std::vector<int32_t>> cnt(nb);
-  parallel_chunks(nb, [&](int b, int) {
-    std::vector<int32_t>& c = cnt[b];
-    c.assign(static_cast<size_t>(m), 0);
-    for (int32_t p = A.ptr[row0(b)]; p < A.ptr[row0(b + 1)]; ++p) c[A.col[p]]++;
-  });
-  // cnt[b][j] becomes block b's first slot within column j
-  const int ncb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(64, m / 4096)));
-  parallel_chunks(ncb, [&](int cb, int) {
-    const int32_t j1 = static_cast<int32_t>(static_cast<int64_t>(m) * (cb + 1) / ncb);
-    for (int32_t j = static_cast<int32_t>(static_cast<int64_t>(m) * cb / ncb); j < j1; ++j) {
-      int32_t sum = 0;
-      for (int b = 0; b < nb; ++b) {
-        const int32_t c = cnt[b][j];
-        cnt[b][j] = sum;
-        sum += c;
-      }
-      T.ptr[j + 1] = sum;
-    }
-  });
-  for (int32_t j = 0; j < m; ++j) T.ptr[j + 1] += T.ptr[j];
-  parallel_chunks(nb, [&](int b, int) {
-    std::vector<int32_t>& c = cnt[b];
-    for (int32_t i = row0(b); i < row0(b + 1); ++i)
-      for (int32_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
-        const int32_t j = A.col[p];
-        const int32_t w = T.ptr[j] + c[j]++;
-        T.col[w] = i;
-        T.val[w] = A.val[p];
-      }
-  });
+  transpose_blocks(A.n_rows, A.n_cols, A.nnz(), A.ptr.data(), A.col.data(), T.ptr.data(),
+                   [&](int64_t w, int32_t i, int32_t p) {
+                     T.col[w] = i;
+                     T.val[w] = A.val[p];
+                   });
   return T;
 }
 
