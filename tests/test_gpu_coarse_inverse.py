@@ -283,3 +283,26 @@ def test_singular_coarsest_is_refused():
     case.vals = v
     with pytest.raises(CprError, match="singular"):
         _solver(case, coarse_max=10 ** 6, coarse_solver=1)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (5, 3, 1), (8, 8, 1), (13, 5, 1), (16, 8, 1)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_inverse_at_panel_boundaries(shape):
+    """Single-level hierarchies of 1, 15, 64, 65 and 128 rows: one partial
+    column panel, exactly one and two full panels, and a full panel plus a
+    one-column panel of the blocked elimination.  The V-cycle is
+    A_P^{-1} r within 100 eps cond(A_P) of LAPACK's solve."""
+    case = bo.case_small(seed=41, shape=shape)
+    A = cpr.Bsr.from_case(case)
+    B = cpr.setup(A, amg.AmgParams(coarse_max=10 ** 6))
+    Ad = B.amg.levels[0].A.to_dense()
+    S = _solver(case, coarse_max=10 ** 6, coarse_solver=1)
+    assert S.level_info(0)["n_levels"] == 1
+    r = np.random.default_rng(43).standard_normal(A.n_b)
+    got = S.vcycle(_dev(r)).cpu().numpy()
+    S.close()
+    want = np.linalg.solve(Ad, r)
+    bound = 100 * np.finfo(np.float64).eps * np.linalg.cond(Ad)
+    d = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(f"[panels {A.n_b}] vcycle diff {d:.2e}, bound {bound:.2e}", flush=True)
+    assert d <= bound
