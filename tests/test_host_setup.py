@@ -248,3 +248,20 @@ def test_host_aggregates_match_oracle(which, npair):
     got, ng = _host_aggregates(A, 0.25, npair)
     assert ng == nw
     assert np.array_equal(got, want)
+
+
+def test_host_aggregates_match_oracle_at_block_parallel_size():
+    """87,750 pressure rows with 588,528 stored entries: large enough that the
+    library's transpose (inside the matching's symmetric part) splits its rows
+    into two blocks and the strong sets are built over 42 row chunks.  The
+    symmetric merge needs every transposed row in ascending column order, so
+    the aggregates equal the oracle's only if the block-parallel transpose
+    keeps that order."""
+    from oracle import uaamg
+
+    A = pressure_matrix(Bsr.from_case(bo.case_spe10_like(seed=95, shape=(60, 60, 25))))
+    assert A.indptr[-1] > 2 * 262144
+    want, nw = uaamg.npair_aggregates(A, 0.25, 2)
+    got, ng = _host_aggregates(A, 0.25, 2)
+    assert ng == nw
+    assert np.array_equal(got, want)
