@@ -275,15 +275,16 @@ def _source_hash(fnames):
     return h.hexdigest()[:16]
 
 
-def _measured_traffic(kernel, workload, amg):
+def _measured_traffic(kernel, workload, method):
     """HBM bytes per launch of a kernel class from the committed counter
-    summary, if it was taken on this workload, with this AMG configuration and
-    on the current sources of the class (else None)."""
+    summary, if it was taken on this workload, with this method configuration
+    (AMG, second stage and decoupling, as `_method_config` names them) and on
+    the current sources of the class (else None)."""
     if workload != "spe10" or not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
         data = json.load(f)
-    if data.get("amg") != amg:
+    if any(data.get(key) != method.get(key) for key in ("amg", "stage2", "decoupling")):
         return None
     rec = data.get("classes", {}).get(kernel)
     if not rec or rec.get("source_sha256_16") != _source_hash(KERNEL_SOURCES[kernel]):
@@ -693,7 +694,7 @@ def main():
         d = kernels[dom]
         roof = {"bound": "hbm", "kernel": dom, "achieved": d["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": d["achieved_GBs"] / HBM_PEAK_GBS,
-                "traffic": _measured_traffic(dom, args.workload, _method_config(args)["amg"])}
+                "traffic": _measured_traffic(dom, args.workload, _method_config(args))}
 
     med32 = statistics.median(r32["times"])
     out = {

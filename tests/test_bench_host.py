@@ -63,12 +63,15 @@ def test_traffic_record_matches_only_its_configuration():
         pytest.skip("no committed counter record")
     with open(bench.TRAFFIC_FILE) as f:
         rec = json.load(f)
-    amg = rec["amg"]
+    method = {key: rec[key] for key in ("amg", "stage2", "decoupling")}
+    assert method == bench._method_config(_args())  # taken with the benchmark's default method
     cls = "pgs_scm_colour_sweep_coarse"
-    got = bench._measured_traffic(cls, "spe10", amg)
+    got = bench._measured_traffic(cls, "spe10", method)
     fresh = rec["classes"][cls]["source_sha256_16"] == bench._source_hash(bench.KERNEL_SOURCES[cls])
     assert (got is not None) == fresh
     if fresh:
         assert got == rec["classes"][cls]["hbm_bytes_per_launch"]
-    assert bench._measured_traffic(cls, "spe10", amg + " (other)") is None
-    assert bench._measured_traffic(cls, "channels", amg) is None
+    for key, other in (("amg", method["amg"] + " (other)"), ("stage2", "block ILU(0), level-scheduled solves"),
+                       ("decoupling", "quasi-IMPES")):
+        assert bench._measured_traffic(cls, "spe10", dict(method, **{key: other})) is None
+    assert bench._measured_traffic(cls, "channels", method) is None
