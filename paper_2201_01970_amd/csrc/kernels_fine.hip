@@ -17,6 +17,19 @@ namespace cpr {
 // has column -1 and zero values, so it reads x at cell 0 and adds zeros.
 constexpr int kSpmvUnroll = 2;
 
+// Loads of matrix blocks that no later kernel reads before they leave the
+// caches: the outer product streams 534 MB of FP64 blocks and the second
+// stage the FP32 copy, more together than the 256 MB last-level cache holds.
+// They are non-temporal so that they do not evict the vectors and AMG levels
+// the following kernels read (measured: product 121.8 -> 113.1 us, FP32
+// solve 11.37 -> 11.18 ms at 3.28M DOF).  The smoothers' matrices are read
+// again by the next sweep and keep ordinary loads (non-temporal ones made the
+// solve slower).
+template <typename P>
+__device__ __forceinline__ P stream_load(const P* p) {
+  return __builtin_nontemporal_load(p);
+}
+
 template <typename TA, typename TX, bool RESID>
 __global__ __launch_bounds__(kBlock) void k_bsr_spmv(int32_t n, const int32_t* __restrict__ slice_ptr,
                                                      const int32_t* __restrict__ col,
@@ -42,11 +55,11 @@ __global__ __launch_bounds__(kBlock) void k_bsr_spmv(int32_t n, const int32_t* _
 #pragma unroll
     for (int u = 0; u < kSpmvUnroll; ++u) {
       const bool live = t + u < t1;
-      const int32_t cw = live ? col[(int64_t)(t + u) * kWave + lane] : kPadCol;
+      const int32_t cw = live ? stream_load(col + (int64_t)(t + u) * kWave + lane) : kPadCol;
       c[u] = cw < 0 ? 0 : cw;
       const TA* vb = val + (int64_t)(t + u) * (9 * kWave) + lane;
 #pragma unroll
-      for (int e = 0; e < 9; ++e) a[u][e] = live ? (double)vb[e * kWave] : 0.0;
+      for (int e = 0; e < 9; ++e) a[u][e] = live ? (double)stream_load(vb + e * kWave) : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < kSpmvUnroll; ++u) {
@@ -164,7 +177,8 @@ __global__ __launch_bounds__(kBlock) void k_stage2(int32_t lo, int32_t hi, const
     // entries together; padded slots (column -1) contribute nothing
     int32_t cw[kStage2Unroll];
 #pragma unroll
-    for (int u = 0; u < kStage2Unroll; ++u) cw[u] = (t + u < s1) ? col[(int64_t)(t + u) * kWave + lane] : kPadCol;
+    for (int u = 0; u < kStage2Unroll; ++u)
+      cw[u] = (t + u < s1) ? stream_load(col + (int64_t)(t + u) * kWave + lane) : kPadCol;
 #pragma unroll
     for (int u = 0; u < kStage2Unroll; ++u) {
       const int32_t c = cw[u];
@@ -173,15 +187,15 @@ __global__ __launch_bounds__(kBlock) void k_stage2(int32_t lo, int32_t hi, const
       const T* vb = val + (int64_t)(t + u) * (9 * kWave) + lane;
       if (c & kEarlierBit) {
         const T z0 = z[3 * j], z1 = z[3 * j + 1], z2 = z[3 * j + 2];
-        const T a00 = vb[0 * kWave], a01 = vb[1 * kWave], a02 = vb[2 * kWave];
-        const T a10 = vb[3 * kWave], a11 = vb[4 * kWave], a12 = vb[5 * kWave];
-        const T a20 = vb[6 * kWave], a21 = vb[7 * kWave], a22 = vb[8 * kWave];
+        const T a00 = stream_load(vb), a01 = stream_load(vb + kWave), a02 = stream_load(vb + 2 * kWave);
+        const T a10 = stream_load(vb + 3 * kWave), a11 = stream_load(vb + 4 * kWave), a12 = stream_load(vb + 5 * kWave);
+        const T a20 = stream_load(vb + 6 * kWave), a21 = stream_load(vb + 7 * kWave), a22 = stream_load(vb + 8 * kWave);
         t0 = t0 - a00 * z0; t0 = t0 - a01 * z1; t0 = t0 - a02 * z2;
         t1 = t1 - a10 * z0; t1 = t1 - a11 * z1; t1 = t1 - a12 * z2;
         t2 = t2 - a20 * z0; t2 = t2 - a21 * z1; t2 = t2 - a22 * z2;
       } else {
         const T p = pe[j];
-        const T a00 = vb[0 * kWave], a10 = vb[3 * kWave], a20 = vb[6 * kWave];
+        const T a00 = stream_load(vb), a10 = stream_load(vb + 3 * kWave), a20 = stream_load(vb + 6 * kWave);
         t0 = t0 - a00 * p;
         t1 = t1 - a10 * p;
         t2 = t2 - a20 * p;
