@@ -501,11 +501,14 @@ __global__ __launch_bounds__(kBlock) void k_dense_gemv(int n, const double* __re
   const double* r = ainv + (int64_t)row * n;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   int j = lane;
+  // the inverse is streamed once per cycle: non-temporal loads keep it from
+  // evicting the level data the next kernels read (22.9 -> 21.8 us at 3702
+  // rows)
   for (; j + 192 < n; j += 256) {
-    a0 = a0 + r[j] * (double)b[j];
-    a1 = a1 + r[j + 64] * (double)b[j + 64];
-    a2 = a2 + r[j + 128] * (double)b[j + 128];
-    a3 = a3 + r[j + 192] * (double)b[j + 192];
+    a0 = a0 + __builtin_nontemporal_load(r + j) * (double)b[j];
+    a1 = a1 + __builtin_nontemporal_load(r + j + 64) * (double)b[j + 64];
+    a2 = a2 + __builtin_nontemporal_load(r + j + 128) * (double)b[j + 128];
+    a3 = a3 + __builtin_nontemporal_load(r + j + 192) * (double)b[j + 192];
   }
   if (j < n) a0 = a0 + r[j] * (double)b[j];
   if (j + 64 < n) a1 = a1 + r[j + 64] * (double)b[j + 64];
