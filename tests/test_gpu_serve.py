@@ -129,3 +129,36 @@ def test_served_requests_match_oracle():
             if n > 0:
                 assert bool(info["rebuilt"]) == rep.rebuilt, (cid, k)
             assert d <= max(1e-8, 5.0 * gap), (cid, k)
+
+
+def test_inverse_coarsest_alone_vs_mix_and_plain_handle():
+    """The coarsest level solved by its explicit inverse (coarse_solver = 1,
+    coarse_max = 400): each SETUP runs its own Gauss-Jordan elimination on its
+    slot's stream, several at once on four slots (the 400-cell case is a
+    single 400-row level).  Every result is bit-identical alone and in the
+    mix, and equal to a plain handle's."""
+    from paper_2201_01970_amd import Params, Solver
+
+    params = Params(precond_fp32=True, coarse_solver=1, coarse_max=400)
+    reqs = _requests()
+    mixed, stats = _run(reqs, slots=4, params=params)
+    print("[serve inverse] stats", stats, flush=True)
+    assert all(info["status"] == "CPR_OK" for _, info in mixed)
+    assert stats["setups"] == 4 and stats["reuses"] == 4
+    for cid in sorted({r[0] for r in reqs}):
+        idx = [k for k, r in enumerate(reqs) if r[0] == cid]
+        alone, _ = _run([reqs[k] for k in idx], slots=1, params=params)
+        for k, (xa, ia) in zip(idx, alone):
+            xm, im = mixed[k]
+            assert np.array_equal(xm, xa), (cid, k)
+            assert im["iterations"] == ia["iterations"] and im["rebuilt"] == ia["rebuilt"]
+    for k in range(3):  # first request of cases 1, 2, 3: a fresh SETUP each
+        cid, c, b = reqs[k]
+        S = Solver(c.row_ptr, c.col, c.vals, params)
+        assert S.level_info(S.level_info(0)["n_levels"] - 1)["n"] <= 400
+        xs, _ = S.solve(torch.as_tensor(b, device="cuda"))
+        assert np.array_equal(xs.cpu().numpy(), mixed[k][0])
+        S.close()
+    for (cid, c, b), (x, info) in zip(reqs, mixed):
+        rel = np.linalg.norm(cpr.bsr_residual(cpr.Bsr.from_case(c), x, b)) / np.linalg.norm(b)
+        assert rel < 1e-6
