@@ -6,7 +6,8 @@ the library's static device array; every sum keeps its order, so the result
 must equal cpr_solve's bit for bit, with the same iteration count and
 residuals.  Two calls in a row, the second on a smaller system (the static
 array keeps the first call's contents), then a restarted solve, the FP32
-preconditioner, and the two refusals: a restart above the array's limit, and
+preconditioner (also with the inverse coarsest level, the aggregation AMG
+with the AMLI-cycle, and block ILU(0) as stage 2), and the two refusals: a restart above the array's limit, and
 a solve for which the adaptive-setup rule asks a SETUP.
 """
 import numpy as np
@@ -70,8 +71,10 @@ def test_two_calls_in_a_row_second_smaller():
 
 
 @pytest.mark.parametrize("kw", [dict(restart=4), dict(precond_fp32=1),
-                                dict(precond_fp32=1, coarse_max=120, coarse_solver=1)],
-                         ids=["restart4", "fp32", "fp32-coarse-inverse"])
+                                dict(precond_fp32=1, coarse_max=120, coarse_solver=1),
+                                dict(precond_fp32=1, amg_kind=1, coarse_max=120),
+                                dict(precond_fp32=1, second_stage=1)],
+                         ids=["restart4", "fp32", "fp32-coarse-inverse", "fp32-aggregation-amli", "fp32-block-ilu0"])
 def test_restarted_and_fp32(kw):
     case = bo.case_small(seed=21, shape=(14, 12, 6))
     b = bo.rhs(case.ndof, 22)
